@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""SDM collision-coalescence benchmark on one MI355X.
+
+Default workload: the large batched grid -- 256 x 256 cells of 2e6 m^3, SD
+count Poisson(256) per cell (about 16.8 M super-droplets), geometric
+sweep-out kernel, 6 extra fp64 extensive attributes, int64 multiplicities,
+per-cell adaptive substepping keeping gamma <= 1, a drizzle mode in a quarter
+of the cells.  Its state (1.07 GB) exceeds the GPU's last-level cache, so it
+is the one on which the HBM-roofline fraction means something.  One step is
+one outer coalescence step of every cell: a single fused launch.
+
+Inputs are synthetic and seeded (paper_2103_17238_amd.inputs), resident in HBM
+before timing starts.  The throughput unit is the super-droplet-step (one live
+SD through one outer step).  Algorithmic bytes per step: 16 per live SD
+(read xi and v), 8 per dead slot (read xi), (32 + 32 A) per colliding pair,
+8 per cell (offsets); see the design doc.
+
+Prints ONE JSON line.  --gpus above 1 is refused: this build measures one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "super-droplet-steps/s (coalescence) + % HBM roofline; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def make_state(name):
+    from paper_2103_17238_amd import inputs as I
+
+    if name == "grid256":
+        return I.grid_256x256(), "grid256x256_poisson256_geometric_adaptive_A6"
+    if name == "grid64":
+        return I.grid_64x64(), "grid64x64_poisson128cap200_geometric_A3"
+    if name == "golovin":
+        return I.golovin_box(2 ** 13, replicas=1024), "golovin_box_2^13_x1024_cells"
+    if name == "geometric":
+        return I.geometric_box(2 ** 17), "geometric_box_2^17"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("sdm_kernels.hip", "sdm_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2103_17238_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_name, workload, launches_bytes):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"{kernel_name}_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    scale = d.get("copy_scale", 1.0)
+    return (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0 * scale
+
+
+def cpu_baseline(state, n_cells_sample, steps):
+    """The CPU oracle, as it stands, on the first cells of the same workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2103_17238_amd import inputs as I
+
+    C = min(n_cells_sample, state.n_cells)
+    end = int(state.cell_off[C])
+    sub = I.State(state.xi[:end].copy(), state.v[:end].copy(),
+                  np.ascontiguousarray(state.attrs[:, :end]), state.cell_off[: C + 1].copy(),
+                  state.dt, state.dv, state.kernel, state.b, state.adaptive, state.seed)
+    threads = min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                  oracle.max_threads())
+    cfg = oracle.OracleConfig(n_slots=sub.n_slots, n_cells=C, n_attr=sub.n_attr, dt=sub.dt,
+                              dv=sub.dv, b=sub.b, kernel=sub.kernel, adaptive=sub.adaptive,
+                              n_threads=threads, seed=sub.seed)
+    live = 0
+    t0 = time.perf_counter()
+    for s in range(steps):
+        out = oracle.step(cfg, sub.xi, sub.v, sub.attrs, sub.cell_off, s)
+        live += int(out["tallies"][0])
+    dt = time.perf_counter() - t0
+    return {"value": live / dt, "unit": "SD-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {C} cells ({sub.n_slots} SD slots) of the same workload, "
+                      f"{steps} steps, OpenMP over cells; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="grid256",
+                    choices=["grid256", "grid64", "golovin", "geometric"])
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cells", type=int, default=4096)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(cells shard across GPUs with no exchange, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2103_17238_amd import binding as B
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    state, workload = make_state(args.workload)
+    host_state = state.copy()
+    sim = B.Sim(state)
+    stream = torch.cuda.current_stream()
+
+    tuning_note = "default"
+    if not args.no_tune:
+        # single-launch shapes only, so that one step is one kernel
+        best = None
+        for wpb in (1, 2, 4, 8):
+            t = B.sdm_get_tuning(sim.handle)
+            t.wave_class_mask, t.waves_per_block = 8, wpb
+            B.sdm_set_tuning(sim.handle, t)
+            # time on a scratch copy so the measured state is untouched
+            probe = B.Sim(host_state)
+            B.sdm_set_tuning(probe.handle, t)
+            probe.step(2)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            probe.step(4)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 4
+            probe.close()
+            if best is None or ms < best[0]:
+                best = (ms, wpb)
+        t = B.sdm_get_tuning(sim.handle)
+        t.wave_class_mask, t.waves_per_block = 8, best[1]
+        B.sdm_set_tuning(sim.handle, t)
+        tuning_note = "autotuned"
+    tuning = B.sdm_get_tuning(sim.handle).as_dict()
+
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    B.sdm_reset_status(sim.handle)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(K):
+        sim.step(1)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    per_launch_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(K)])
+    total_ms = float(evs[0].elapsed_time(evs[K]))
+    stats = B.sdm_stats(sim.handle)
+    flags = B.sdm_status_word(sim.handle)
+
+    live = stats["live_sd_steps"]
+    coll = stats["colliding_pairs"]
+    A = state.n_attr
+    alg_bytes = (16 * live + 8 * (K * state.n_slots - live) + (32 + 32 * A) * coll
+                 + 8 * state.n_cells * K)
+    value = live / (total_ms / 1e3)
+    single_launch = args.workload in ("grid256", "grid64")
+    kernel_name = "k_wave_cells_512" if single_launch else "whole_step"
+    achieved = alg_bytes / K / (per_launch_ms.mean() / 1e3) / 1e9
+    traffic = traffic_from_profiles(kernel_name, args.workload, alg_bytes / K)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "SD-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generators: Poisson cell sizes, lognormal radii)",
+        "config": {
+            "workload": workload,
+            "cells": state.n_cells,
+            "sd_slots": state.n_slots,
+            "n_attr": A,
+            "kernel": "geometric" if state.kernel == 1 else "golovin",
+            "adaptive": bool(state.adaptive),
+            "parallelism": "1 GPU, one fused launch per step" if single_launch else "1 GPU",
+            "tuning": tuning,
+            "tuning_source": tuning_note,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kernel_name,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes / K,
+            "avg_launch_ms": float(per_launch_ms.mean()),
+        },
+        "stats": {"live_sd_steps": live, "colliding_pairs": coll,
+                  "cell_substeps": stats["cell_substeps"], "cell_steps": stats["cell_steps"],
+                  "status_flags": flags, "wall_s": t_wall},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(host_state, args.cpu_cells, args.cpu_steps)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * sdm.h -- C ABI of libsdm: the Super-Droplet Method (SDM) Monte-Carlo
+ * collision-coalescence step on AMD Instinct MI355X (gfx950).
+ *
+ * The operation.  The PySDM v1 paper (arXiv 2103.17238) builds a simulation
+ * from a super-droplet count and a backend ("API in brief": Builder(n_sd,
+ * backend)), a Box environment of time step dt and volume dV, the
+ * Coalescence dynamic with a collision kernel such as Golovin(b), and the
+ * initial attributes 'volume' and 'n' (multiplicity); it is advanced with
+ * run(n_steps) and read through products such as the dv/dlnr spectrum.  The
+ * coalescence step is the SDM of Shima et al. (2009), which the paper names as
+ * the package core ("Introduction").  Here:
+ *   sdm_init             <-> Builder + Box + Coalescence + build(attributes)
+ *   sdm_coalescence_step <-> run(n_steps)
+ *   sdm_moments          <-> the dv/dlnr product (and total moments)
+ * Per step and per cell: a random permutation of the live super-droplets (SDs)
+ * from 32-bit Philox4x32-10 keys ordered by (key, slot); neighbour pairs;
+ * the pair probability p = max(xi_a, xi_b) K(v_a, v_b) dt/dV scaled by
+ * n(n-1)/2 / floor(n/2); gamma = floor(p) + [phi < p - floor(p)] from a 53-bit
+ * uniform phi; and the multiplicity / extensive-attribute update with the
+ * equal-multiplicity split.  Kernels: Golovin K = b (v1 + v2) ("API in
+ * brief") and geometric sweep-out K = pi (r1 + r2)^2 |u1 - u2| with the
+ * continuous three-regime terminal velocity of Rogers & Yau (1989) ("Box
+ * environment examples", the Berry 1966 example).  Every random number is a
+ * function of (seed, cell, step, substep, index) only, so results do not
+ * depend on launch shape, batching or tuning.
+ *
+ * Memory and ownership.
+ *   - Every pointer argument named dev_* or documented as "device" is device
+ *     memory owned by the caller (e.g. torch tensors).  The library borrows
+ *     the state arrays (xi, v, attrs, cell_off) and the workspace for the
+ *     lifetime of the handle; it never allocates or frees device memory.
+ *   - The library allocates only the host-side handle; sdm_free releases it.
+ *   - Layout is structure-of-arrays: xi[n_slots] (int64), v[n_slots] (float64,
+ *     m^3), attrs[n_attr][n_slots] (float64, extra extensive attributes summed
+ *     on coalescence like volume), cell_off[n_cells + 1] (int64, slots of cell
+ *     c are [cell_off[c], cell_off[c+1]), cell_off[0] = 0, cell_off[n_cells] =
+ *     n_slots).  An SD with xi = 0 is dead and keeps its slot.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Errors.  Every call returns an sdm_status; nothing aborts and no exception
+ * crosses the ABI.  Device-side conditions set bits of a per-simulation status
+ * word (sdm_status_word).
+ *
+ * Threading.  Step and moments calls only enqueue work on `stream` and return.
+ * One handle must not be stepped on two streams at once.
+ */
+#ifndef SDM_H
+#define SDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdm_sim sdm_sim;     /* opaque host handle of one simulation */
+typedef struct sdm_batch sdm_batch; /* opaque group of simulations stepped by shared launches */
+
+typedef enum {
+  SDM_OK = 0,
+  SDM_EINVAL = -1,  /* bad argument, configuration or initial state */
+  SDM_ENOMEM = -2,  /* workspace too small */
+  SDM_EDEVICE = -3, /* a HIP call failed */
+  SDM_ESTATE = -4,  /* call not valid in the handle's current state */
+  SDM_EAGAIN = -5   /* resource busy */
+} sdm_status;
+
+typedef enum { SDM_GOLOVIN = 0, SDM_GEOMETRIC = 1 } sdm_kernel_kind;
+
+/* bits of the device status word */
+#define SDM_FLAG_SUBSTEP_CAP 1u     /* adaptive: max_substeps reached, remainder done unclamped */
+#define SDM_FLAG_GAMMA_CAP 2u       /* some p >= 2^62: gamma capped at 2^62 */
+#define SDM_FLAG_BUCKET_OVERFLOW 4u /* big-cell sort used its slow path (still exact) */
+#define SDM_FLAG_INVALID_STATE 8u   /* validation found xi < 0, xi >= 2^53 or a bad volume */
+
+typedef struct {
+  int64_t n_slots;        /* SD slots (live and dead), >= 0 */
+  int32_t n_cells;        /* >= 1 */
+  int32_t n_attr;         /* extra extensive attributes, 0..16 */
+  double dt_s;            /* time step [s], > 0 (Box dt) */
+  double dv_m3;           /* cell volume [m^3], > 0 (Box dv) */
+  int32_t kernel;         /* sdm_kernel_kind */
+  int32_t adaptive;       /* 1: per-cell substepping keeping gamma <= 1 */
+  double golovin_b_per_s; /* Golovin b [1/s] (volume-based kernel), >= 0 */
+  uint64_t seed;          /* Philox key */
+  int32_t max_substeps;   /* adaptive substep cap per step (0 = 1024) */
+  int32_t reserved;       /* must be 0 */
+} sdm_config;
+
+/* Launch-shape knobs.  They change speed only, never results. */
+typedef struct {
+  int32_t wave_class_mask;   /* bit k (k = 0..3): cells of <= 64 << k slots get their own
+                                one-wave-per-cell launch; cells go to the smallest enabled
+                                class that fits; bit 3 (512) is always on */
+  int32_t waves_per_block;   /* 1, 2, 4 or 8 cells (waves) per workgroup */
+  int32_t big_bucket_target; /* cells > 512 slots: expected SDs per sort bucket, 32..1024 */
+  int32_t lpt_order;         /* 1: dispatch cells by descending size */
+} sdm_tuning;
+
+/*
+ * Workspace bytes sdm_init needs.  host_cell_off (optional, host memory,
+ * n_cells + 1 entries) gives the exact size for that cell layout; with NULL
+ * the result is an upper bound valid for any layout.  Returns 0 on a bad cfg.
+ */
+size_t sdm_workspace_bytes(const sdm_config* cfg, const int64_t* host_cell_off);
+
+/*
+ * Create a simulation over caller-owned device state (see "Memory and
+ * ownership").  attrs may be NULL when n_attr = 0.  workspace: device memory
+ * of at least sdm_workspace_bytes bytes, 256-byte aligned.  Copies cell_off
+ * to the host, validates cfg and the state (one kernel, then a stream
+ * synchronisation), and plans the launches.  The step counter starts at 0.
+ * Returns SDM_EINVAL for a bad cfg/state (also: adaptive mode with a cell of
+ * more than 512 slots), SDM_ENOMEM if the workspace is too small.
+ */
+sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v, double* attrs,
+                    const int64_t* cell_off, void* workspace, size_t workspace_bytes,
+                    void* stream);
+
+/* Advance n_steps >= 0 outer steps (enqueue only). Steps beyond the step limit are skipped. */
+sdm_status sdm_coalescence_step(sdm_sim* s, int32_t n_steps, void* stream);
+
+/*
+ * Per-cell moments of the live SDs, written to device buffers (any may be
+ * NULL): m0[C] = sum xi (int64, exact); m12[C][2] = (sum xi v, sum xi v^2);
+ * attr_sums[C][A] = sum xi a_q; spectrum[C][n_bins] = sum xi v over SDs with
+ * vol_edges[k] <= v < vol_edges[k+1] (vol_edges: device, n_bins + 1 increasing
+ * volumes [m^3]; SDs outside are dropped).  dm/dlnr of bin k is
+ * rho_w spectrum / dV / ln(r_{k+1} / r_k).  Sums use a fixed reduction order,
+ * so a cell's moments do not depend on the rest of the state.
+ */
+sdm_status sdm_moments(sdm_sim* s, int64_t* m0, double* m12, double* attr_sums,
+                       const double* vol_edges, int32_t n_bins, double* spectrum, void* stream);
+
+/* Device status word (SDM_FLAG_* bits); synchronises `stream`. */
+sdm_status sdm_status_word(sdm_sim* s, uint32_t* flags, void* stream);
+/* Clear the status word and the statistics counters (enqueue). */
+sdm_status sdm_reset_status(sdm_sim* s, void* stream);
+
+/*
+ * Statistics accumulated since init / reset (synchronises `stream`):
+ * out[0] live SD-steps (live SDs at the start of each outer step, summed),
+ * out[1] colliding pairs (gamma > 0), out[2] cell substeps, out[3] cell steps.
+ */
+sdm_status sdm_stats(sdm_sim* s, uint64_t out[4], void* stream);
+
+/* Step counter (outer steps taken; the Philox counter word). */
+uint32_t sdm_get_step(const sdm_sim* s);
+sdm_status sdm_set_step(sdm_sim* s, uint32_t step);
+/* Steps at or beyond `limit` are skipped (UINT32_MAX = no limit). */
+sdm_status sdm_set_step_limit(sdm_sim* s, uint32_t limit);
+
+/*
+ * Test hook: per candidate pair of the last (sub)step, dev_buf[2 i] =
+ * a | (b << 32) (cell-local slots of the pair), dev_buf[2 i + 1] = gamma,
+ * where cell c's pairs start at i = sum over c' < c of floor(slots(c') / 2);
+ * unused entries are -1.  capacity is in int64 elements (>= 2 x that total).
+ * NULL turns the sink off.
+ */
+sdm_status sdm_debug_gamma_sink(sdm_sim* s, int64_t* dev_buf, int64_t capacity);
+
+/* Launch-shape knobs: get, set (re-plans; same results), and an autotuner. */
+sdm_status sdm_get_tuning(const sdm_sim* s, sdm_tuning* t);
+sdm_status sdm_set_tuning(sdm_sim* s, const sdm_tuning* t, void* stream);
+/*
+ * Time candidate tunings on a scratch copy of the state (scratch: device,
+ * >= sdm_autotune_scratch_bytes) for trial_steps steps each, apply the
+ * fastest to s and, if cache_path is not NULL, record it in that JSON file
+ * keyed by device, kernel, n_attr, mode and a cell-size histogram; a cached
+ * entry is reused without timing.  s's own state and step counter are not
+ * touched.  chosen (optional) receives the tuning.
+ */
+size_t sdm_autotune_scratch_bytes(const sdm_sim* s);
+sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_bytes, int32_t trial_steps,
+                        const char* cache_path, sdm_tuning* chosen, void* stream);
+
+/*
+ * Batches: simulations stepped together by shared launches (one launch per
+ * step covers every member's cells).  Members keep their own state, seed,
+ * kernel, counters and status.  workspace: device, >= sdm_batch_workspace_bytes.
+ * Members must stay alive while the batch exists.
+ */
+size_t sdm_batch_workspace_bytes(sdm_sim* const* sims, int32_t n);
+sdm_status sdm_batch_create(sdm_batch** out, sdm_sim* const* sims, int32_t n, void* workspace,
+                            size_t workspace_bytes, void* stream);
+/* Advance every member n_steps (each member honours its own step limit). */
+sdm_status sdm_batch_step(sdm_batch* b, int32_t n_steps, void* stream);
+void sdm_batch_free(sdm_batch* b);
+
+void sdm_free(sdm_sim* s);
+const char* sdm_strerror(sdm_status st);
+
+/*
+ * Test hook for the generator: out[4 i + w] = word w of Philox4x32-10 with
+ * counter (c0 + i, c1, c2, c3) and key (seed mod 2^32, seed / 2^32), for
+ * i < n (device buffer of 4 n uint32).  Enqueue only.
+ */
+sdm_status sdm_philox_fill(uint32_t* out, int64_t n, uint32_t c0, uint32_t c1, uint32_t c2,
+                           uint32_t c3, uint64_t seed, void* stream);
+
+/* Test hook: K(v1[i], v2[i]) for n pairs of device volumes into device out. */
+sdm_status sdm_kernel_values(int32_t kernel, double golovin_b, const double* v1, const double* v2,
+                             int64_t n, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDM_H */

@@ -1,0 +1,830 @@
+// sdm_api.cpp -- host driver behind include/sdm.h: validation, launch
+// planning (cell-size classes, big-cell buckets), workspace carving, batches
+// of simulations sharing launches, statistics and the autotuner.
+//
+// The mapping to the PySDM v1 paper's API ("API in brief"): sdm_init plays
+// Builder(n_sd, backend) + Box(dt, dv) + Coalescence(kernel) + build(attributes),
+// sdm_coalescence_step plays Particulator.run(n_steps) with the step counter
+// n_steps, and sdm_moments the product registry (dv/dlnr spectrum).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sdm.h"
+#include "sdm_internal.hpp"
+
+using sdm::BigBucket;
+using sdm::BigChunk;
+using sdm::BigPairBlock;
+using sdm::BigTask;
+using sdm::PlanDev;
+using sdm::SimDesc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int ceil_log2(int64_t x) {
+  int b = 0;
+  while ((int64_t(1) << b) < x) ++b;
+  return b;
+}
+
+sdm_tuning default_tuning() {
+  sdm_tuning t;
+  t.wave_class_mask = 0xF;
+  t.waves_per_block = 4;
+  t.big_bucket_target = 256;
+  t.lpt_order = 1;
+  return t;
+}
+
+bool tuning_ok(const sdm_tuning& t) {
+  const int w = t.waves_per_block;
+  return (w == 1 || w == 2 || w == 4 || w == 8) && t.big_bucket_target >= sdm::kMinBucketTarget &&
+         t.big_bucket_target <= 1024 && (t.wave_class_mask & ~0xF) == 0;
+}
+
+}  // namespace
+
+struct Plan;
+
+struct sdm_sim {
+  sdm_config cfg{};
+  int64_t* xi = nullptr;
+  double* v = nullptr;
+  double* attrs = nullptr;
+  const int64_t* cell_off = nullptr;
+  std::vector<int64_t> off;  // host copy of cell_off
+  uint32_t step = 0;
+  uint32_t limit = 0xFFFFFFFFu;
+  sdm_tuning tuning = default_tuning();
+  int64_t* sink = nullptr;
+  int64_t sink_cap = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t* d_status = nullptr;
+  unsigned long long* d_stats = nullptr;
+  int64_t* d_pair_base = nullptr;
+  Plan* plan = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Launch plan over a list of simulations
+// ---------------------------------------------------------------------------
+struct Tables {
+  std::vector<int2> wave[sdm::kNumClasses];
+  std::vector<BigTask> big;
+  std::vector<BigChunk> chunks;
+  std::vector<BigBucket> buckets;
+  std::vector<BigPairBlock> pblocks;
+  int64_t tmp_total = 0;
+  int64_t bucket_total = 0;
+  int64_t n_wave_total() const {
+    int64_t n = 0;
+    for (auto& w : wave) n += (int64_t)w.size();
+    return n;
+  }
+};
+
+static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, Tables& T) {
+  struct Item {
+    int64_t n;
+    int sim, cell;
+  };
+  std::vector<Item> items[sdm::kNumClasses];
+  const int mask = tu.wave_class_mask | 0x8;
+  for (int i = 0; i < (int)ms.size(); ++i) {
+    const auto& off = ms[i]->off;
+    const int C = ms[i]->cfg.n_cells;
+    for (int c = 0; c < C; ++c) {
+      const int64_t n = off[c + 1] - off[c];
+      if (n <= 0) continue;
+      if (n <= sdm::kWaveCapMax) {
+        int k = 0;
+        while (!((mask >> k) & 1) || n > sdm::class_cap(k)) ++k;
+        items[k].push_back({n, i, c});
+        continue;
+      }
+      BigTask t{};
+      t.sim = i;
+      t.cell = c;
+      t.n_slots = (int32_t)n;
+      const int64_t want = (n + tu.big_bucket_target - 1) / tu.big_bucket_target;
+      t.bbits = want <= 1 ? 0 : ceil_log2(want);
+      t.tmp_base = T.tmp_total;
+      T.tmp_total += n;
+      t.bucket_base = (int32_t)T.bucket_total;
+      const int nb = 1 << t.bbits;
+      T.bucket_total += nb + 1;
+      const int ti = (int)T.big.size();
+      T.big.push_back(t);
+      for (int64_t f = 0; f < n; f += sdm::kChunk) T.chunks.push_back({ti, (int32_t)f});
+      for (int b = 0; b < nb; ++b) T.buckets.push_back({ti, b});
+      const int64_t groups = (n + 3) / 4;
+      for (int64_t g = 0; g < groups; g += 256) T.pblocks.push_back({ti, (int32_t)g});
+    }
+  }
+  for (int k = 0; k < sdm::kNumClasses; ++k) {
+    auto& v = items[k];
+    if (tu.lpt_order)
+      std::stable_sort(v.begin(), v.end(), [](const Item& a, const Item& b) { return a.n > b.n; });
+    T.wave[k].resize(v.size());
+    for (size_t j = 0; j < v.size(); ++j) T.wave[k][j] = make_int2(v[j].sim, v[j].cell);
+  }
+}
+
+struct Layout {
+  size_t desc, wave[sdm::kNumClasses], big, chunks, buckets, pblocks, bucket_cnt, bucket_start,
+      task_live, task_nlive, tmp, ord, total;
+};
+
+static Layout layout_of(int n_members, const Tables& T) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  L.desc = take(sizeof(SimDesc) * std::max(n_members, 1));
+  for (int k = 0; k < sdm::kNumClasses; ++k)
+    L.wave[k] = take(sizeof(int2) * std::max<size_t>(T.wave[k].size(), 1));
+  L.big = take(sizeof(BigTask) * std::max<size_t>(T.big.size(), 1));
+  L.chunks = take(sizeof(BigChunk) * std::max<size_t>(T.chunks.size(), 1));
+  L.buckets = take(sizeof(BigBucket) * std::max<size_t>(T.buckets.size(), 1));
+  L.pblocks = take(sizeof(BigPairBlock) * std::max<size_t>(T.pblocks.size(), 1));
+  L.bucket_cnt = take(sizeof(uint32_t) * std::max<int64_t>(T.bucket_total, 1));
+  L.bucket_start = take(sizeof(uint32_t) * std::max<int64_t>(T.bucket_total, 1));
+  L.task_live = take(sizeof(uint32_t) * std::max<size_t>(T.big.size(), 1));
+  L.task_nlive = take(sizeof(uint32_t) * std::max<size_t>(T.big.size(), 1));
+  L.tmp = take(sizeof(unsigned long long) * std::max<int64_t>(T.tmp_total, 1));
+  L.ord = take(sizeof(uint32_t) * std::max<int64_t>(T.tmp_total, 1));
+  L.total = o;
+  return L;
+}
+
+// plan bytes for the worst-case tuning (smallest bucket target, all classes)
+static size_t plan_bytes_worst(const std::vector<sdm_sim*>& ms) {
+  sdm_tuning t = default_tuning();
+  t.big_bucket_target = sdm::kMinBucketTarget;
+  Tables T;
+  build_tables(ms, t, T);
+  return layout_of((int)ms.size(), T).total;
+}
+
+struct Plan {
+  std::vector<sdm_sim*> members;
+  sdm_tuning tuning = default_tuning();
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Tables T;
+  PlanDev dev{};
+  std::vector<SimDesc> desc;  // host copy of the device descriptors
+  uint32_t counter = 0;       // launch step of the next step
+};
+
+static SimDesc make_desc(const sdm_sim* s, uint32_t delta) {
+  SimDesc d{};
+  d.xi = s->xi;
+  d.v = s->v;
+  d.attrs = s->attrs;
+  d.cell_off = s->cell_off;
+  d.status = s->d_status;
+  d.stats = s->d_stats;
+  d.sink = s->sink;
+  d.pair_base = s->d_pair_base;
+  d.n_slots = s->cfg.n_slots;
+  d.q = s->cfg.dt_s / s->cfg.dv_m3;
+  d.dt = s->cfg.dt_s;
+  d.dv = s->cfg.dv_m3;
+  d.b = s->cfg.golovin_b_per_s;
+  d.seed_lo = (uint32_t)(s->cfg.seed & 0xFFFFFFFFull);
+  d.seed_hi = (uint32_t)(s->cfg.seed >> 32);
+  d.step_delta = delta;
+  d.step_limit = s->limit;
+  d.n_attr = s->cfg.n_attr;
+  d.kernel = s->cfg.kernel;
+  d.adaptive = s->cfg.adaptive;
+  d.max_substeps = s->cfg.max_substeps > 0 ? s->cfg.max_substeps : 1024;
+  return d;
+}
+
+#define HIP_TRY(x)                        \
+  do {                                    \
+    if ((x) != hipSuccess) {              \
+      (void)hipGetLastError();            \
+      return SDM_EDEVICE;                 \
+    }                                     \
+  } while (0)
+
+template <typename T>
+static hipError_t upload(T* dst, const std::vector<T>& src) {
+  if (src.empty()) return hipSuccess;
+  return hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+// (Re)build the plan tables for its members and upload them; syncs `st` first.
+static sdm_status plan_setup(Plan* p, hipStream_t st) {
+  p->T = Tables();
+  build_tables(p->members, p->tuning, p->T);
+  const Layout L = layout_of((int)p->members.size(), p->T);
+  if (L.total > p->ws_bytes) return SDM_ENOMEM;
+  char* w = p->ws;
+  PlanDev& d = p->dev;
+  d.desc = reinterpret_cast<const SimDesc*>(w + L.desc);
+  for (int k = 0; k < sdm::kNumClasses; ++k) {
+    d.wave_tasks[k] = reinterpret_cast<const int2*>(w + L.wave[k]);
+    d.n_wave[k] = (int)p->T.wave[k].size();
+  }
+  d.big = reinterpret_cast<const BigTask*>(w + L.big);
+  d.n_big = (int)p->T.big.size();
+  d.chunks = reinterpret_cast<const BigChunk*>(w + L.chunks);
+  d.n_chunks = (int)p->T.chunks.size();
+  d.buckets = reinterpret_cast<const BigBucket*>(w + L.buckets);
+  d.n_buckets = (int)p->T.buckets.size();
+  d.pblocks = reinterpret_cast<const BigPairBlock*>(w + L.pblocks);
+  d.n_pblocks = (int)p->T.pblocks.size();
+  d.bucket_cnt = reinterpret_cast<uint32_t*>(w + L.bucket_cnt);
+  d.bucket_start = reinterpret_cast<uint32_t*>(w + L.bucket_start);
+  d.task_live = reinterpret_cast<uint32_t*>(w + L.task_live);
+  d.task_nlive = reinterpret_cast<uint32_t*>(w + L.task_nlive);
+  d.tmp = reinterpret_cast<unsigned long long*>(w + L.tmp);
+  d.ord = reinterpret_cast<uint32_t*>(w + L.ord);
+
+  HIP_TRY(hipStreamSynchronize(st));
+  p->desc.clear();
+  for (auto* s : p->members) p->desc.push_back(make_desc(s, s->step - p->counter));
+  HIP_TRY(upload(const_cast<SimDesc*>(d.desc), p->desc));
+  for (int k = 0; k < sdm::kNumClasses; ++k)
+    HIP_TRY(upload(const_cast<int2*>(d.wave_tasks[k]), p->T.wave[k]));
+  HIP_TRY(upload(const_cast<BigTask*>(d.big), p->T.big));
+  HIP_TRY(upload(const_cast<BigChunk*>(d.chunks), p->T.chunks));
+  HIP_TRY(upload(const_cast<BigBucket*>(d.buckets), p->T.buckets));
+  HIP_TRY(upload(const_cast<BigPairBlock*>(d.pblocks), p->T.pblocks));
+  if (p->T.bucket_total > 0)
+    HIP_TRY(hipMemset(d.bucket_cnt, 0, sizeof(uint32_t) * p->T.bucket_total));
+  if (!p->T.big.empty()) HIP_TRY(hipMemset(d.task_live, 0, sizeof(uint32_t) * p->T.big.size()));
+  HIP_TRY(hipDeviceSynchronize());
+  return SDM_OK;
+}
+
+// descriptors must follow member step counters, limits and sinks
+static sdm_status plan_refresh(Plan* p, hipStream_t st) {
+  bool changed = false;
+  for (size_t i = 0; i < p->members.size(); ++i) {
+    const SimDesc want = make_desc(p->members[i], p->members[i]->step - p->counter);
+    if (std::memcmp(&want, &p->desc[i], sizeof(SimDesc)) != 0) {
+      p->desc[i] = want;
+      changed = true;
+    }
+  }
+  if (!changed) return SDM_OK;
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(upload(const_cast<SimDesc*>(p->dev.desc), p->desc));
+  return SDM_OK;
+}
+
+static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
+  if (n_steps < 0) return SDM_EINVAL;
+  if (n_steps == 0) return SDM_OK;
+  sdm_status r = plan_refresh(p, st);
+  if (r != SDM_OK) return r;
+  // steps any member still takes
+  int64_t active = 0;
+  for (auto* s : p->members) {
+    const int64_t left = s->step < s->limit ? (int64_t)(s->limit - s->step) : 0;
+    active = std::max<int64_t>(active, std::min<int64_t>(left, n_steps));
+  }
+  for (int64_t k = 0; k < active; ++k) {
+    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->tuning.waves_per_block, st) !=
+        hipSuccess)
+      return SDM_EDEVICE;
+  }
+  p->counter += (uint32_t)n_steps;
+  for (auto* s : p->members) {
+    const int64_t left = s->step < s->limit ? (int64_t)(s->limit - s->step) : 0;
+    s->step += (uint32_t)std::min<int64_t>(left, n_steps);
+  }
+  // keep descriptors consistent: members that hit their limit get re-synced lazily
+  return SDM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Simulation handle
+// ---------------------------------------------------------------------------
+static size_t sim_region_bytes(int32_t n_cells) {
+  return align_up(sizeof(uint32_t)) +
+         align_up(sizeof(unsigned long long) * sdm::kStatSlots * sdm::kStatFields) +
+         align_up(sizeof(int64_t) * ((size_t)n_cells + 1));
+}
+
+static bool cfg_ok(const sdm_config* c) {
+  if (!c) return false;
+  if (c->n_slots < 0 || c->n_cells < 1 || c->n_attr < 0 || c->n_attr > 16) return false;
+  if (!(c->dt_s > 0.0) || !(c->dv_m3 > 0.0) || !std::isfinite(c->dt_s) ||
+      !std::isfinite(c->dv_m3))
+    return false;
+  if (c->kernel != SDM_GOLOVIN && c->kernel != SDM_GEOMETRIC) return false;
+  if (!(c->golovin_b_per_s >= 0.0) || !std::isfinite(c->golovin_b_per_s)) return false;
+  if (c->adaptive != 0 && c->adaptive != 1) return false;
+  if (c->max_substeps < 0 || c->reserved != 0) return false;
+  if (c->n_slots > 0x7FFFFFFFLL) return false;
+  return true;
+}
+
+static bool offsets_ok(const sdm_config* c, const int64_t* off) {
+  if (off[0] != 0 || off[c->n_cells] != c->n_slots) return false;
+  for (int i = 0; i < c->n_cells; ++i)
+    if (off[i + 1] < off[i]) return false;
+  return true;
+}
+
+static size_t plan_bytes_for(const sdm_config* cfg, const int64_t* off) {
+  sdm_sim tmp;
+  tmp.cfg = *cfg;
+  tmp.off.assign(off, off + cfg->n_cells + 1);
+  std::vector<sdm_sim*> ms{&tmp};
+  return plan_bytes_worst(ms);
+}
+
+static size_t plan_bytes_bound(const sdm_config* c) {
+  const int64_t ns = c->n_slots, C = c->n_cells;
+  const int64_t nbig = std::min<int64_t>(C, ns / (sdm::kWaveCapMax + 1));
+  Tables T;  // sizes only
+  size_t o = 0;
+  auto take = [&](size_t b) { o += align_up(b); };
+  take(sizeof(SimDesc));
+  for (int k = 0; k < sdm::kNumClasses; ++k) take(sizeof(int2) * (size_t)std::max<int64_t>(C, 1));
+  take(sizeof(BigTask) * (size_t)std::max<int64_t>(nbig, 1));
+  take(sizeof(BigChunk) * (size_t)(ns / sdm::kChunk + nbig + 1));
+  const int64_t nbk = ns / (sdm::kMinBucketTarget / 2) + 2 * nbig + 1;
+  take(sizeof(BigBucket) * (size_t)nbk);
+  take(sizeof(BigPairBlock) * (size_t)(ns / 1024 + nbig + 1));
+  take(sizeof(uint32_t) * (size_t)(nbk + nbig));
+  take(sizeof(uint32_t) * (size_t)(nbk + nbig));
+  take(sizeof(uint32_t) * (size_t)std::max<int64_t>(nbig, 1));
+  take(sizeof(uint32_t) * (size_t)std::max<int64_t>(nbig, 1));
+  take(sizeof(unsigned long long) * (size_t)std::max<int64_t>(ns, 1));
+  take(sizeof(uint32_t) * (size_t)std::max<int64_t>(ns, 1));
+  (void)T;
+  return o;
+}
+
+extern "C" {
+
+size_t sdm_workspace_bytes(const sdm_config* cfg, const int64_t* host_cell_off) {
+  if (!cfg_ok(cfg)) return 0;
+  const size_t plan = host_cell_off ? (offsets_ok(cfg, host_cell_off)
+                                           ? plan_bytes_for(cfg, host_cell_off)
+                                           : 0)
+                                    : plan_bytes_bound(cfg);
+  if (host_cell_off && plan == 0) return 0;
+  return sim_region_bytes(cfg->n_cells) + plan;
+}
+
+sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v, double* attrs,
+                    const int64_t* cell_off, void* workspace, size_t workspace_bytes,
+                    void* stream) {
+  if (!out) return SDM_EINVAL;
+  *out = nullptr;
+  if (!cfg_ok(cfg) || !cell_off || !workspace) return SDM_EINVAL;
+  if (cfg->n_slots > 0 && (!xi || !v)) return SDM_EINVAL;
+  if (cfg->n_attr > 0 && cfg->n_slots > 0 && !attrs) return SDM_EINVAL;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return SDM_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  sdm::set_lds_limits();
+
+  sdm_sim* s = new (std::nothrow) sdm_sim();
+  if (!s) return SDM_ENOMEM;
+  s->cfg = *cfg;
+  if (s->cfg.max_substeps == 0) s->cfg.max_substeps = 1024;
+  s->xi = xi;
+  s->v = v;
+  s->attrs = cfg->n_attr > 0 ? attrs : nullptr;
+  s->cell_off = cell_off;
+  s->off.resize((size_t)cfg->n_cells + 1);
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(s->off.data(), cell_off, sizeof(int64_t) * s->off.size(),
+                hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    delete s;
+    return SDM_EDEVICE;
+  }
+  if (!offsets_ok(cfg, s->off.data())) {
+    delete s;
+    return SDM_EINVAL;
+  }
+  if (cfg->adaptive) {
+    for (int c = 0; c < cfg->n_cells; ++c)
+      if (s->off[c + 1] - s->off[c] > sdm::kWaveCapMax) {
+        delete s;
+        return SDM_EINVAL;
+      }
+  }
+  const size_t need = sim_region_bytes(cfg->n_cells) + plan_bytes_for(cfg, s->off.data());
+  if (workspace_bytes < need) {
+    delete s;
+    return SDM_ENOMEM;
+  }
+  char* w = static_cast<char*>(workspace);
+  s->ws = w;
+  s->ws_bytes = workspace_bytes;
+  s->d_status = reinterpret_cast<uint32_t*>(w);
+  w += align_up(sizeof(uint32_t));
+  s->d_stats = reinterpret_cast<unsigned long long*>(w);
+  w += align_up(sizeof(unsigned long long) * sdm::kStatSlots * sdm::kStatFields);
+  s->d_pair_base = reinterpret_cast<int64_t*>(w);
+  w += align_up(sizeof(int64_t) * ((size_t)cfg->n_cells + 1));
+
+  std::vector<int64_t> pb((size_t)cfg->n_cells + 1, 0);
+  for (int c = 0; c < cfg->n_cells; ++c) pb[c + 1] = pb[c] + (s->off[c + 1] - s->off[c]) / 2;
+  bool ok = hipMemset(s->d_status, 0, sizeof(uint32_t)) == hipSuccess &&
+            hipMemset(s->d_stats, 0,
+                      sizeof(unsigned long long) * sdm::kStatSlots * sdm::kStatFields) ==
+                hipSuccess &&
+            hipMemcpy(s->d_pair_base, pb.data(), sizeof(int64_t) * pb.size(),
+                      hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && sdm::launch_validate(xi, v, cfg->n_slots, s->d_status, st) == hipSuccess;
+  uint32_t flags = 0;
+  ok = ok && hipStreamSynchronize(st) == hipSuccess &&
+       hipMemcpy(&flags, s->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    delete s;
+    return SDM_EDEVICE;
+  }
+  if (flags & sdm::kFlagInvalid) {
+    delete s;
+    return SDM_EINVAL;
+  }
+  s->plan = new (std::nothrow) Plan();
+  if (!s->plan) {
+    delete s;
+    return SDM_ENOMEM;
+  }
+  s->plan->members = {s};
+  s->plan->ws = w;
+  s->plan->ws_bytes = workspace_bytes - (size_t)(w - static_cast<char*>(workspace));
+  s->plan->tuning = s->tuning;
+  const sdm_status r = plan_setup(s->plan, st);
+  if (r != SDM_OK) {
+    delete s->plan;
+    delete s;
+    return r;
+  }
+  *out = s;
+  return SDM_OK;
+}
+
+sdm_status sdm_coalescence_step(sdm_sim* s, int32_t n_steps, void* stream) {
+  if (!s || n_steps < 0) return SDM_EINVAL;
+  s->plan->counter = s->step;
+  return plan_step(s->plan, n_steps, reinterpret_cast<hipStream_t>(stream));
+}
+
+sdm_status sdm_moments(sdm_sim* s, int64_t* m0, double* m12, double* attr_sums,
+                       const double* vol_edges, int32_t n_bins, double* spectrum, void* stream) {
+  if (!s || n_bins < 0) return SDM_EINVAL;
+  if (spectrum && (!vol_edges || n_bins < 1)) return SDM_EINVAL;
+  const SimDesc d = make_desc(s, 0);
+  if (sdm::launch_moments(d, s->cfg.n_cells, m0, m12, attr_sums, vol_edges,
+                          spectrum ? n_bins : 0, spectrum,
+                          reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return SDM_EDEVICE;
+  return SDM_OK;
+}
+
+sdm_status sdm_status_word(sdm_sim* s, uint32_t* flags, void* stream) {
+  if (!s || !flags) return SDM_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(flags, s->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SDM_OK;
+}
+
+sdm_status sdm_reset_status(sdm_sim* s, void* stream) {
+  if (!s) return SDM_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemsetAsync(s->d_status, 0, sizeof(uint32_t), st));
+  HIP_TRY(hipMemsetAsync(s->d_stats, 0,
+                         sizeof(unsigned long long) * sdm::kStatSlots * sdm::kStatFields, st));
+  return SDM_OK;
+}
+
+sdm_status sdm_stats(sdm_sim* s, uint64_t out[4], void* stream) {
+  if (!s || !out) return SDM_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<unsigned long long> h((size_t)sdm::kStatSlots * sdm::kStatFields);
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(h.data(), s->d_stats, sizeof(unsigned long long) * h.size(),
+                    hipMemcpyDeviceToHost));
+  for (int f = 0; f < 4; ++f) out[f] = 0;
+  for (int i = 0; i < sdm::kStatSlots; ++i)
+    for (int f = 0; f < sdm::kStatFields; ++f) out[f] += h[(size_t)i * sdm::kStatFields + f];
+  return SDM_OK;
+}
+
+uint32_t sdm_get_step(const sdm_sim* s) { return s ? s->step : 0u; }
+
+sdm_status sdm_set_step(sdm_sim* s, uint32_t step) {
+  if (!s) return SDM_EINVAL;
+  s->step = step;
+  return SDM_OK;
+}
+
+sdm_status sdm_set_step_limit(sdm_sim* s, uint32_t limit) {
+  if (!s) return SDM_EINVAL;
+  s->limit = limit;
+  return SDM_OK;
+}
+
+sdm_status sdm_debug_gamma_sink(sdm_sim* s, int64_t* dev_buf, int64_t capacity) {
+  if (!s) return SDM_EINVAL;
+  if (dev_buf) {
+    int64_t pairs = 0;
+    for (int c = 0; c < s->cfg.n_cells; ++c) pairs += (s->off[c + 1] - s->off[c]) / 2;
+    if (capacity < 2 * pairs) return SDM_EINVAL;
+  }
+  s->sink = dev_buf;
+  s->sink_cap = dev_buf ? capacity : 0;
+  return SDM_OK;
+}
+
+sdm_status sdm_get_tuning(const sdm_sim* s, sdm_tuning* t) {
+  if (!s || !t) return SDM_EINVAL;
+  *t = s->tuning;
+  return SDM_OK;
+}
+
+sdm_status sdm_set_tuning(sdm_sim* s, const sdm_tuning* t, void* stream) {
+  if (!s || !t || !tuning_ok(*t)) return SDM_EINVAL;
+  s->tuning = *t;
+  s->tuning.wave_class_mask |= 0x8;
+  s->plan->tuning = s->tuning;
+  s->plan->counter = s->step;
+  return plan_setup(s->plan, reinterpret_cast<hipStream_t>(stream));
+}
+
+void sdm_free(sdm_sim* s) {
+  if (!s) return;
+  delete s->plan;
+  delete s;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct sdm_batch {
+  Plan plan;
+};
+
+size_t sdm_batch_workspace_bytes(sdm_sim* const* sims, int32_t n) {
+  if (!sims || n < 1) return 0;
+  std::vector<sdm_sim*> ms(sims, sims + n);
+  for (auto* s : ms)
+    if (!s) return 0;
+  return plan_bytes_worst(ms);
+}
+
+sdm_status sdm_batch_create(sdm_batch** out, sdm_sim* const* sims, int32_t n, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  if (!out || !sims || n < 1 || !workspace) return SDM_EINVAL;
+  *out = nullptr;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return SDM_EINVAL;
+  sdm_batch* b = new (std::nothrow) sdm_batch();
+  if (!b) return SDM_ENOMEM;
+  b->plan.members.assign(sims, sims + n);
+  for (auto* s : b->plan.members)
+    if (!s) {
+      delete b;
+      return SDM_EINVAL;
+    }
+  b->plan.ws = static_cast<char*>(workspace);
+  b->plan.ws_bytes = workspace_bytes;
+  b->plan.tuning = b->plan.members[0]->tuning;
+  b->plan.counter = 0;
+  const sdm_status r = plan_setup(&b->plan, reinterpret_cast<hipStream_t>(stream));
+  if (r != SDM_OK) {
+    delete b;
+    return r;
+  }
+  *out = b;
+  return SDM_OK;
+}
+
+sdm_status sdm_batch_step(sdm_batch* b, int32_t n_steps, void* stream) {
+  if (!b) return SDM_EINVAL;
+  return plan_step(&b->plan, n_steps, reinterpret_cast<hipStream_t>(stream));
+}
+
+void sdm_batch_free(sdm_batch* b) { delete b; }
+
+const char* sdm_strerror(sdm_status st) {
+  switch (st) {
+    case SDM_OK: return "ok";
+    case SDM_EINVAL: return "invalid argument, configuration or state";
+    case SDM_ENOMEM: return "workspace too small";
+    case SDM_EDEVICE: return "HIP runtime error";
+    case SDM_ESTATE: return "call not valid in this state";
+    case SDM_EAGAIN: return "resource busy";
+  }
+  return "unknown status";
+}
+
+sdm_status sdm_philox_fill(uint32_t* out, int64_t n, uint32_t c0, uint32_t c1, uint32_t c2,
+                           uint32_t c3, uint64_t seed, void* stream) {
+  if (n < 0 || (n > 0 && !out)) return SDM_EINVAL;
+  if (sdm::launch_philox_fill(out, n, c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32),
+                              reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return SDM_EDEVICE;
+  return SDM_OK;
+}
+
+sdm_status sdm_kernel_values(int32_t kernel, double golovin_b, const double* v1, const double* v2,
+                             int64_t n, double* out, void* stream) {
+  if (n < 0 || (n > 0 && (!v1 || !v2 || !out))) return SDM_EINVAL;
+  if (kernel != SDM_GOLOVIN && kernel != SDM_GEOMETRIC) return SDM_EINVAL;
+  if (sdm::launch_kernel_values(kernel, golovin_b, v1, v2, n, out,
+                                reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return SDM_EDEVICE;
+  return SDM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner (sdm_autotune): times candidate launch shapes on a scratch copy
+// of the state.  Results never depend on the tuning, only speed does.
+// ---------------------------------------------------------------------------
+static std::string tune_key(const sdm_sim* s) {
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  // share of slots per size class (<=64, <=128, <=256, <=512, >512), in 5 % steps
+  int64_t cls[5] = {0, 0, 0, 0, 0};
+  int64_t big_max = 0;
+  for (int c = 0; c < s->cfg.n_cells; ++c) {
+    const int64_t n = s->off[c + 1] - s->off[c];
+    int k = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
+    cls[k] += n;
+    big_max = std::max(big_max, n);
+  }
+  const double tot = (double)std::max<int64_t>(s->cfg.n_slots, 1);
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s/cu%d/k%d/a%d/ad%d/l2n%d/c%d-%d-%d-%d-%d/b%d",
+                prop.gcnArchName, prop.multiProcessorCount, s->cfg.kernel, s->cfg.n_attr,
+                s->cfg.adaptive, ceil_log2(std::max<int64_t>(s->cfg.n_slots, 1)),
+                (int)std::lround(20 * cls[0] / tot), (int)std::lround(20 * cls[1] / tot),
+                (int)std::lround(20 * cls[2] / tot), (int)std::lround(20 * cls[3] / tot),
+                (int)std::lround(20 * cls[4] / tot), ceil_log2(std::max<int64_t>(big_max, 1)));
+  return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, sdm_tuning* t) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[512];
+    sdm_tuning x{};
+    double ms = 0;
+    if (std::sscanf(line,
+                    "{\"key\": \"%511[^\"]\", \"wave_class_mask\": %d, \"waves_per_block\": %d, "
+                    "\"big_bucket_target\": %d, \"lpt_order\": %d, \"ms_per_step\": %lf}",
+                    k, &x.wave_class_mask, &x.waves_per_block, &x.big_bucket_target,
+                    &x.lpt_order, &ms) == 6 &&
+        key == k && tuning_ok(x)) {
+      *t = x;  // the last matching line wins
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void cache_store(const char* path, const std::string& key, const sdm_tuning& t, double ms) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"key\": \"%s\", \"wave_class_mask\": %d, \"waves_per_block\": %d, "
+               "\"big_bucket_target\": %d, \"lpt_order\": %d, \"ms_per_step\": %.6f}\n",
+               key.c_str(), t.wave_class_mask, t.waves_per_block, t.big_bucket_target,
+               t.lpt_order, ms);
+  std::fclose(f);
+}
+
+extern "C" size_t sdm_autotune_scratch_bytes(const sdm_sim* s) {
+  if (!s) return 0;
+  const size_t ns = (size_t)s->cfg.n_slots;
+  return align_up(ns * 8) + align_up(ns * 8) + align_up(ns * 8 * (size_t)s->cfg.n_attr) +
+         sim_region_bytes(s->cfg.n_cells) + plan_bytes_for(&s->cfg, s->off.data());
+}
+
+extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_bytes,
+                                   int32_t trial_steps, const char* cache_path,
+                                   sdm_tuning* chosen, void* stream) {
+  if (!s || trial_steps < 1) return SDM_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const std::string key = tune_key(s);
+  sdm_tuning best{};
+  if (cache_path && cache_lookup(cache_path, key, &best)) {
+    const sdm_status r = sdm_set_tuning(s, &best, stream);
+    if (r == SDM_OK && chosen) *chosen = s->tuning;
+    return r;
+  }
+  if (!scratch || scratch_bytes < sdm_autotune_scratch_bytes(s) ||
+      reinterpret_cast<uintptr_t>(scratch) % kAlign)
+    return SDM_ENOMEM;
+  const size_t ns = (size_t)s->cfg.n_slots;
+  char* w = static_cast<char*>(scratch);
+  int64_t* xi2 = reinterpret_cast<int64_t*>(w);
+  w += align_up(ns * 8);
+  double* v2 = reinterpret_cast<double*>(w);
+  w += align_up(ns * 8);
+  double* a2 = s->cfg.n_attr ? reinterpret_cast<double*>(w) : nullptr;
+  w += align_up(ns * 8 * (size_t)s->cfg.n_attr);
+  const size_t ws_left = scratch_bytes - (size_t)(w - static_cast<char*>(scratch));
+
+  auto restore = [&]() {
+    bool ok = hipMemcpyAsync(xi2, s->xi, ns * 8, hipMemcpyDeviceToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(v2, s->v, ns * 8, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    if (a2)
+      ok = ok && hipMemcpyAsync(a2, s->attrs, ns * 8 * (size_t)s->cfg.n_attr,
+                                hipMemcpyDeviceToDevice, st) == hipSuccess;
+    return ok;
+  };
+
+  // candidate shapes
+  bool has_small[4] = {false, false, false, false}, has_big = false;
+  for (int c = 0; c < s->cfg.n_cells; ++c) {
+    const int64_t n = s->off[c + 1] - s->off[c];
+    if (n > sdm::kWaveCapMax) has_big = true;
+    else if (n > 0) has_small[n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3] = true;
+  }
+  std::vector<int> masks = {0x8};
+  for (int m : {0xC, 0xE, 0xF, 0xA, 0x9}) {  // only masks that split populated classes
+    bool useful = false;
+    for (int k = 0; k < 3; ++k)
+      if (((m >> k) & 1) && has_small[k]) useful = true;
+    if (useful) masks.push_back(m);
+  }
+  std::vector<int> targets = has_big ? std::vector<int>{64, 128, 256, 512} : std::vector<int>{256};
+  std::vector<sdm_tuning> cands;
+  for (int m : masks)
+    for (int wpb : {1, 2, 4, 8})
+      for (int tg : targets) cands.push_back({m, wpb, tg, 1});
+
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best_ms = 1e300;
+  bool any = false;
+  for (const auto& cand : cands) {
+    if (!restore()) return SDM_EDEVICE;
+    sdm_sim* t = nullptr;
+    sdm_config cfg = s->cfg;
+    if (sdm_init(&t, &cfg, xi2, v2, a2, s->cell_off, w, ws_left, stream) != SDM_OK) continue;
+    t->step = s->step;
+    if (sdm_set_tuning(t, &cand, stream) != SDM_OK) {
+      sdm_free(t);
+      continue;
+    }
+    bool ok = sdm_coalescence_step(t, 1, stream) == SDM_OK;  // warm-up
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    ok = ok && sdm_coalescence_step(t, trial_steps, stream) == SDM_OK;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    sdm_free(t);
+    if (!ok) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return SDM_EDEVICE;
+    }
+    const double per = ms / trial_steps;
+    if (per < best_ms) {
+      best_ms = per;
+      best = cand;
+      any = true;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!any) return SDM_EDEVICE;
+  const sdm_status r = sdm_set_tuning(s, &best, stream);
+  if (r != SDM_OK) return r;
+  if (cache_path) cache_store(cache_path, key, s->tuning, best_ms);
+  if (chosen) *chosen = s->tuning;
+  return SDM_OK;
+}

@@ -1,0 +1,110 @@
+// sdm_internal.hpp -- types shared by the HIP kernels and the host driver of
+// libsdm (not part of the public ABI, see include/sdm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdm {
+
+constexpr int kStatSlots = 256;   // spread of the statistics counters (fewer atomics per address)
+constexpr int kStatFields = 4;    // live SD-steps, colliding pairs, cell substeps, cell steps
+constexpr int kNumClasses = 4;    // one-wave-per-cell capacities 64, 128, 256, 512 slots
+constexpr int kWaveCapMax = 512;  // cells above this go to the big-cell path
+constexpr int kChunk = 1024;      // slots per block in the big-cell key passes
+constexpr int kBucketCap = 1024;  // big-cell bucket entries staged in LDS by one wave
+constexpr int kMinBucketTarget = 32;
+
+constexpr uint32_t kFlagSubstepCap = 1u;
+constexpr uint32_t kFlagGammaCap = 2u;
+constexpr uint32_t kFlagBucketOverflow = 4u;
+constexpr uint32_t kFlagInvalid = 8u;
+
+inline int class_cap(int k) { return 64 << k; }
+
+// Per-simulation parameters read by every step kernel (device array, one per member).
+struct SimDesc {
+  int64_t* xi;
+  double* v;
+  double* attrs;  // [n_attr][n_slots]
+  const int64_t* cell_off;
+  uint32_t* status;
+  unsigned long long* stats;  // [kStatSlots][kStatFields]
+  int64_t* sink;              // optional gamma sink
+  const int64_t* pair_base;   // per-cell first pair index of the sink
+  int64_t n_slots;
+  double q;   // dt / dV
+  double dt;  // s
+  double dv;  // m^3
+  double b;   // Golovin b [1/s]
+  uint32_t seed_lo, seed_hi;
+  uint32_t step_delta;  // member step = launch step + step_delta
+  uint32_t step_limit;  // member steps >= limit are skipped
+  int32_t n_attr;
+  int32_t kernel;
+  int32_t adaptive;
+  int32_t max_substeps;
+};
+
+// A cell of more than kWaveCapMax slots, sorted through global buckets.
+struct BigTask {
+  int32_t sim;
+  int32_t cell;
+  int64_t tmp_base;     // first entry of this cell in the keyed-entry and order buffers
+  int32_t bucket_base;  // first of this cell's (1 << bbits) + 1 bucket counters
+  int32_t bbits;        // log2 of the bucket count
+  int32_t n_slots;
+  int32_t pad;
+};
+
+struct BigChunk {  // kChunk consecutive slots of one big cell
+  int32_t task;
+  int32_t first;
+};
+
+struct BigBucket {  // one bucket of one big cell
+  int32_t task;
+  int32_t bucket;
+};
+
+struct BigPairBlock {  // 256 pair groups (4 sorted positions each) of one big cell
+  int32_t task;
+  int32_t first_group;
+};
+
+// Device view of a launch plan (all pointers carved from a workspace).
+struct PlanDev {
+  const SimDesc* desc;
+  const int2* wave_tasks[kNumClasses];
+  int n_wave[kNumClasses];
+  const BigTask* big;
+  int n_big;
+  const BigChunk* chunks;
+  int n_chunks;
+  const BigBucket* buckets;
+  int n_buckets;
+  const BigPairBlock* pblocks;
+  int n_pblocks;
+  uint32_t* bucket_cnt;
+  uint32_t* bucket_start;
+  uint32_t* task_live;
+  uint32_t* task_nlive;
+  unsigned long long* tmp;
+  uint32_t* ord;
+};
+
+// launches (sdm_kernels.hip)
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_block, hipStream_t st);
+hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
+                          double* attr_sums, const double* edges, int n_bins, double* spectrum,
+                          hipStream_t st);
+hipError_t launch_validate(const int64_t* xi, const double* v, int64_t n, uint32_t* status,
+                           hipStream_t st);
+hipError_t launch_philox_fill(uint32_t* out, int64_t n, uint32_t c0, uint32_t c1, uint32_t c2,
+                              uint32_t c3, uint32_t k0, uint32_t k1, hipStream_t st);
+hipError_t launch_kernel_values(int kind, double b, const double* v1, const double* v2, int64_t n,
+                                double* out, hipStream_t st);
+size_t wave_lds_bytes(int cls);
+void set_lds_limits();
+
+}  // namespace sdm
