@@ -135,7 +135,7 @@ def main():
         best = None
         for wpb in (1, 2, 4, 8):
             t = B.sdm_get_tuning(sim.handle)
-            t.wave_class_mask, t.waves_per_block = 8, wpb
+            t.wave_class_mask, t.waves_per_cell = 8, wpb
             B.sdm_set_tuning(sim.handle, t)
             # time on a scratch copy so the measured state is untouched
             probe = B.Sim(host_state)
@@ -151,7 +151,7 @@ def main():
             if best is None or ms < best[0]:
                 best = (ms, wpb)
         t = B.sdm_get_tuning(sim.handle)
-        t.wave_class_mask, t.waves_per_block = 8, best[1]
+        t.wave_class_mask, t.waves_per_cell = 8, best[1]
         B.sdm_set_tuning(sim.handle, t)
         tuning_note = "autotuned"
     tuning = B.sdm_get_tuning(sim.handle).as_dict()

@@ -92,9 +92,9 @@ typedef struct {
 /* Launch-shape knobs.  They change speed only, never results. */
 typedef struct {
   int32_t wave_class_mask;   /* bit k (k = 0..3): cells of <= 64 << k slots get their own
-                                one-wave-per-cell launch; cells go to the smallest enabled
+                                workgroup-per-cell launch; cells go to the smallest enabled
                                 class that fits; bit 3 (512) is always on */
-  int32_t waves_per_block;   /* 1, 2, 4 or 8 cells (waves) per workgroup */
+  int32_t waves_per_cell;    /* 1, 2, 4 or 8: wavefronts in the workgroup of one cell */
   int32_t big_bucket_target; /* cells > 512 slots: expected SDs per sort bucket, 32..1024 */
   int32_t lpt_order;         /* 1: dispatch cells by descending size */
 } sdm_tuning;

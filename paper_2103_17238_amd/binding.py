@@ -51,7 +51,7 @@ class sdm_config(C.Structure):
 class sdm_tuning(C.Structure):
     _fields_ = [
         ("wave_class_mask", C.c_int32),
-        ("waves_per_block", C.c_int32),
+        ("waves_per_cell", C.c_int32),
         ("big_bucket_target", C.c_int32),
         ("lpt_order", C.c_int32),
     ]

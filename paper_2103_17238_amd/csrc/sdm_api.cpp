@@ -41,14 +41,14 @@ inline int ceil_log2(int64_t x) {
 sdm_tuning default_tuning() {
   sdm_tuning t;
   t.wave_class_mask = 0xF;
-  t.waves_per_block = 4;
+  t.waves_per_cell = 1;
   t.big_bucket_target = 256;
   t.lpt_order = 1;
   return t;
 }
 
 bool tuning_ok(const sdm_tuning& t) {
-  const int w = t.waves_per_block;
+  const int w = t.waves_per_cell;
   return (w == 1 || w == 2 || w == 4 || w == 8) && t.big_bucket_target >= sdm::kMinBucketTarget &&
          t.big_bucket_target <= 1024 && (t.wave_class_mask & ~0xF) == 0;
 }
@@ -81,7 +81,8 @@ struct sdm_sim {
 // Launch plan over a list of simulations
 // ---------------------------------------------------------------------------
 struct Tables {
-  std::vector<int2> wave[sdm::kNumClasses];
+  std::vector<sdm::CellTask> wave[sdm::kNumClasses];  // plain-mode cells first, then adaptive
+  int n_plain[sdm::kNumClasses] = {0, 0, 0, 0};
   std::vector<BigTask> big;
   std::vector<BigChunk> chunks;
   std::vector<BigBucket> buckets;
@@ -98,7 +99,7 @@ struct Tables {
 static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, Tables& T) {
   struct Item {
     int64_t n;
-    int sim, cell;
+    int sim, cell, adaptive;
   };
   std::vector<Item> items[sdm::kNumClasses];
   const int mask = tu.wave_class_mask | 0x8;
@@ -111,7 +112,7 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
       if (n <= sdm::kWaveCapMax) {
         int k = 0;
         while (!((mask >> k) & 1) || n > sdm::class_cap(k)) ++k;
-        items[k].push_back({n, i, c});
+        items[k].push_back({n, i, c, ms[i]->cfg.adaptive});
         continue;
       }
       BigTask t{};
@@ -135,10 +136,23 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
   }
   for (int k = 0; k < sdm::kNumClasses; ++k) {
     auto& v = items[k];
-    if (tu.lpt_order)
-      std::stable_sort(v.begin(), v.end(), [](const Item& a, const Item& b) { return a.n > b.n; });
+    std::stable_sort(v.begin(), v.end(), [&](const Item& a, const Item& b) {
+      if (a.adaptive != b.adaptive) return a.adaptive < b.adaptive;
+      return tu.lpt_order ? a.n > b.n : false;
+    });
+    T.n_plain[k] = 0;
+    for (auto& it : v) T.n_plain[k] += it.adaptive ? 0 : 1;
     T.wave[k].resize(v.size());
-    for (size_t j = 0; j < v.size(); ++j) T.wave[k][j] = make_int2(v[j].sim, v[j].cell);
+    for (size_t j = 0; j < v.size(); ++j) {
+      const sdm_sim* m = ms[v[j].sim];
+      sdm::CellTask& ct = T.wave[k][j];
+      ct.xi = m->xi + m->off[v[j].cell];
+      ct.v = m->v + m->off[v[j].cell];
+      ct.n = (int32_t)v[j].n;
+      ct.sim = v[j].sim;
+      ct.cell = v[j].cell;
+      ct.pad = 0;
+    }
   }
 }
 
@@ -157,7 +171,7 @@ static Layout layout_of(int n_members, const Tables& T) {
   };
   L.desc = take(sizeof(SimDesc) * std::max(n_members, 1));
   for (int k = 0; k < sdm::kNumClasses; ++k)
-    L.wave[k] = take(sizeof(int2) * std::max<size_t>(T.wave[k].size(), 1));
+    L.wave[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(T.wave[k].size(), 1));
   L.big = take(sizeof(BigTask) * std::max<size_t>(T.big.size(), 1));
   L.chunks = take(sizeof(BigChunk) * std::max<size_t>(T.chunks.size(), 1));
   L.buckets = take(sizeof(BigBucket) * std::max<size_t>(T.buckets.size(), 1));
@@ -178,7 +192,8 @@ static size_t plan_bytes_worst(const std::vector<sdm_sim*>& ms) {
   t.big_bucket_target = sdm::kMinBucketTarget;
   Tables T;
   build_tables(ms, t, T);
-  return layout_of((int)ms.size(), T).total;
+  // other class masks split the same cells differently: one alignment pad per class
+  return layout_of((int)ms.size(), T).total + sdm::kNumClasses * kAlign;
 }
 
 struct Plan {
@@ -232,18 +247,34 @@ static hipError_t upload(T* dst, const std::vector<T>& src) {
   return hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
 }
 
+// LDS one workgroup may use on the current device
+static size_t lds_block_limit() {
+  int dev = 0, a = 0, b = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    a = 64 * 1024;
+  if (hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) b = 0;
+  (void)hipGetLastError();
+  return (size_t)std::max(a, b);
+}
+
 // (Re)build the plan tables for its members and upload them; syncs `st` first.
 static sdm_status plan_setup(Plan* p, hipStream_t st) {
   p->T = Tables();
   build_tables(p->members, p->tuning, p->T);
+  for (int k = 0; k < sdm::kNumClasses; ++k)  // every used class must fit one workgroup's LDS
+    if (!p->T.wave[k].empty() && sdm::cell_lds_bytes(k) > lds_block_limit()) return SDM_EINVAL;
   const Layout L = layout_of((int)p->members.size(), p->T);
   if (L.total > p->ws_bytes) return SDM_ENOMEM;
   char* w = p->ws;
   PlanDev& d = p->dev;
+  d.geo = 0;
+  for (auto* s : p->members) d.geo |= (s->cfg.kernel == SDM_GEOMETRIC) ? 1 : 0;
   d.desc = reinterpret_cast<const SimDesc*>(w + L.desc);
   for (int k = 0; k < sdm::kNumClasses; ++k) {
-    d.wave_tasks[k] = reinterpret_cast<const int2*>(w + L.wave[k]);
+    d.wave_tasks[k] = reinterpret_cast<const sdm::CellTask*>(w + L.wave[k]);
     d.n_wave[k] = (int)p->T.wave[k].size();
+    d.n_plain[k] = p->T.n_plain[k];
   }
   d.big = reinterpret_cast<const BigTask*>(w + L.big);
   d.n_big = (int)p->T.big.size();
@@ -265,7 +296,7 @@ static sdm_status plan_setup(Plan* p, hipStream_t st) {
   for (auto* s : p->members) p->desc.push_back(make_desc(s, s->step - p->counter));
   HIP_TRY(upload(const_cast<SimDesc*>(d.desc), p->desc));
   for (int k = 0; k < sdm::kNumClasses; ++k)
-    HIP_TRY(upload(const_cast<int2*>(d.wave_tasks[k]), p->T.wave[k]));
+    HIP_TRY(upload(const_cast<sdm::CellTask*>(d.wave_tasks[k]), p->T.wave[k]));
   HIP_TRY(upload(const_cast<BigTask*>(d.big), p->T.big));
   HIP_TRY(upload(const_cast<BigChunk*>(d.chunks), p->T.chunks));
   HIP_TRY(upload(const_cast<BigBucket*>(d.buckets), p->T.buckets));
@@ -305,7 +336,7 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
     active = std::max<int64_t>(active, std::min<int64_t>(left, n_steps));
   }
   for (int64_t k = 0; k < active; ++k) {
-    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->tuning.waves_per_block, st) !=
+    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->tuning.waves_per_cell, st) !=
         hipSuccess)
       return SDM_EDEVICE;
   }
@@ -363,7 +394,8 @@ static size_t plan_bytes_bound(const sdm_config* c) {
   size_t o = 0;
   auto take = [&](size_t b) { o += align_up(b); };
   take(sizeof(SimDesc));
-  for (int k = 0; k < sdm::kNumClasses; ++k) take(sizeof(int2) * (size_t)std::max<int64_t>(C, 1));
+  for (int k = 0; k < sdm::kNumClasses; ++k)
+    take(sizeof(sdm::CellTask) * (size_t)std::max<int64_t>(C, 1));
   take(sizeof(BigTask) * (size_t)std::max<int64_t>(nbig, 1));
   take(sizeof(BigChunk) * (size_t)(ns / sdm::kChunk + nbig + 1));
   const int64_t nbk = ns / (sdm::kMinBucketTarget / 2) + 2 * nbig + 1;
@@ -700,9 +732,9 @@ static bool cache_lookup(const char* path, const std::string& key, sdm_tuning* t
     sdm_tuning x{};
     double ms = 0;
     if (std::sscanf(line,
-                    "{\"key\": \"%511[^\"]\", \"wave_class_mask\": %d, \"waves_per_block\": %d, "
+                    "{\"key\": \"%511[^\"]\", \"wave_class_mask\": %d, \"waves_per_cell\": %d, "
                     "\"big_bucket_target\": %d, \"lpt_order\": %d, \"ms_per_step\": %lf}",
-                    k, &x.wave_class_mask, &x.waves_per_block, &x.big_bucket_target,
+                    k, &x.wave_class_mask, &x.waves_per_cell, &x.big_bucket_target,
                     &x.lpt_order, &ms) == 6 &&
         key == k && tuning_ok(x)) {
       *t = x;  // the last matching line wins
@@ -717,9 +749,9 @@ static void cache_store(const char* path, const std::string& key, const sdm_tuni
   FILE* f = std::fopen(path, "a");
   if (!f) return;
   std::fprintf(f,
-               "{\"key\": \"%s\", \"wave_class_mask\": %d, \"waves_per_block\": %d, "
+               "{\"key\": \"%s\", \"wave_class_mask\": %d, \"waves_per_cell\": %d, "
                "\"big_bucket_target\": %d, \"lpt_order\": %d, \"ms_per_step\": %.6f}\n",
-               key.c_str(), t.wave_class_mask, t.waves_per_block, t.big_bucket_target,
+               key.c_str(), t.wave_class_mask, t.waves_per_cell, t.big_bucket_target,
                t.lpt_order, ms);
   std::fclose(f);
 }

@@ -9,7 +9,7 @@ namespace sdm {
 
 constexpr int kStatSlots = 256;   // spread of the statistics counters (fewer atomics per address)
 constexpr int kStatFields = 4;    // live SD-steps, colliding pairs, cell substeps, cell steps
-constexpr int kNumClasses = 4;    // one-wave-per-cell capacities 64, 128, 256, 512 slots
+constexpr int kNumClasses = 4;    // workgroup-per-cell capacities 64, 128, 256, 512 slots
 constexpr int kWaveCapMax = 512;  // cells above this go to the big-cell path
 constexpr int kChunk = 1024;      // slots per block in the big-cell key passes
 constexpr int kBucketCap = 1024;  // big-cell bucket entries staged in LDS by one wave
@@ -46,6 +46,17 @@ struct SimDesc {
   int32_t max_substeps;
 };
 
+// A cell of at most kWaveCapMax slots, processed by one workgroup; the entry
+// carries the cell's own xi / v pointers so that fetching it takes one hop.
+struct CellTask {
+  int64_t* xi;  // first slot of the cell
+  double* v;
+  int32_t n;  // slots
+  int32_t sim;
+  int32_t cell;
+  int32_t pad;
+};
+
 // A cell of more than kWaveCapMax slots, sorted through global buckets.
 struct BigTask {
   int32_t sim;
@@ -75,8 +86,10 @@ struct BigPairBlock {  // 256 pair groups (4 sorted positions each) of one big c
 // Device view of a launch plan (all pointers carved from a workspace).
 struct PlanDev {
   const SimDesc* desc;
-  const int2* wave_tasks[kNumClasses];
+  int geo;  // 1 if any member uses the geometric kernel
+  const CellTask* wave_tasks[kNumClasses];  // per class: plain-mode cells first, then adaptive
   int n_wave[kNumClasses];
+  int n_plain[kNumClasses];
   const BigTask* big;
   int n_big;
   const BigChunk* chunks;
@@ -94,7 +107,7 @@ struct PlanDev {
 };
 
 // launches (sdm_kernels.hip)
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_block, hipStream_t st);
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st);
 hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
                           double* attr_sums, const double* edges, int n_bins, double* spectrum,
                           hipStream_t st);
@@ -104,7 +117,7 @@ hipError_t launch_philox_fill(uint32_t* out, int64_t n, uint32_t c0, uint32_t c1
                               uint32_t c3, uint32_t k0, uint32_t k1, hipStream_t st);
 hipError_t launch_kernel_values(int kind, double b, const double* v1, const double* v2, int64_t n,
                                 double* out, hipStream_t st);
-size_t wave_lds_bytes(int cls);
+size_t cell_lds_bytes(int cls);
 void set_lds_limits();
 
 }  // namespace sdm

@@ -26,6 +26,8 @@
 // Floating point: fp64 throughout, built with -ffp-contract=off; the only
 // fused operation is the explicit fma of the update.
 
+#include <algorithm>
+
 #include "sdm_internal.hpp"
 
 namespace sdm {
@@ -38,11 +40,10 @@ namespace sdm {
 __device__ __forceinline__ uint4 philox(uint4 x, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * x.x;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, x.x);
-    const uint32_t lo1 = 0xCD9E8D57u * x.z;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, x.z);
-    x = make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+    const unsigned long long p0 = (unsigned long long)0xD2511F53u * x.x;
+    const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * x.z;
+    x = make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ x.w ^ k1,
+                   (uint32_t)p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -175,111 +176,200 @@ __device__ __forceinline__ void update_pair(XI* xs, VV* vs, int ia, int ib, long
 }
 
 // ---------------------------------------------------------------------------
-// One wavefront per cell (cells of <= CAP slots).
+// One workgroup ("team" of W wavefronts) per cell of <= CAP slots.
+//
+// Every phase spreads its work over the W*64 threads, so a cell's dependent
+// chain of LDS round trips is W times shorter and a SIMD holds W times more
+// independent instruction streams for the same LDS per cell.  LDS per slot:
+// xi and v in slot order (16 B), one 32-bit word that first holds the
+// bucketed (key, slot) entries and then the 16-bit permutation, and one
+// 32-bit bucket counter that later holds the pairs' pre-products.  In the
+// sort a thread owns 4 consecutive slots, i.e. exactly the 4 words of one
+// Philox call, so keys never go through LDS.
 // ---------------------------------------------------------------------------
 template <int CAP>
-struct WaveLds {
-  long long xs[CAP];  // multiplicities of the cell (slot order)
+struct CellLds {
+  long long xs[CAP];  // multiplicities (slot order)
   double vs[CAP];     // volumes (slot order)
-  uint32_t keys[CAP];
-  uint32_t tmp[CAP];  // bucketed (key << nbits | slot); reused for pair pre-products
-  uint32_t cnt[CAP + 4];
-  uint16_t ord[CAP];  // live slots in permuted order
-  uint8_t dirty[CAP];
+  uint32_t tmp[CAP];  // bucketed (key << nbits | slot), then uint16 permutation
+  uint32_t cnt[CAP + 4];     // bucket counters / starts, then double pre-products
+  uint32_t dirty[CAP / 32];  // adaptive mode: slots to write back
+  int red_i[8];              // cross-wave reductions
+  double red_d[8];
 };
 
-// keys, bucket count, scan, scatter, rank: L.ord[0..nlive) = permutation
+template <int W>
+__device__ __forceinline__ void team_sync() {
+  if (W == 1)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+template <int W, int CAP>
+__device__ __forceinline__ int team_sum(CellLds<CAP>& L, int x, int lane, int wv) {
+  x = wave_sum(x);
+  if (W == 1) return x;
+  if (lane == 0) L.red_i[wv] = x;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) t += L.red_i[k];
+  __syncthreads();
+  return t;
+}
+
+template <int W, int CAP>
+__device__ __forceinline__ double team_max(CellLds<CAP>& L, double x, int lane, int wv) {
+  x = wave_max(x);
+  if (W == 1) return x;
+  if (lane == 0) L.red_d[wv] = x;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) t = fmax(t, L.red_d[k]);
+  __syncthreads();
+  return t;
+}
+
 template <int CAP>
-__device__ __forceinline__ void wave_sort(WaveLds<CAP>& L, int n, int nlive, int lane, int c,
-                                          uint32_t s, uint32_t u, uint32_t k0, uint32_t k1) {
-  constexpr int IT = CAP / 64;
-  for (int g0 = 0; 4 * g0 < n; g0 += 64) {
-    const int g = g0 + lane;
+__device__ __forceinline__ uint16_t* perm_of(CellLds<CAP>& L) {
+  return reinterpret_cast<uint16_t*>(L.tmp);
+}
+
+// keys, bucket count, scan, scatter, rank: permutation of the nlive live slots
+template <int CAP, int W>
+__device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int tid, int lane,
+                                          int wv, int c, uint32_t s, uint32_t u, uint32_t k0,
+                                          uint32_t k1) {
+  constexpr int T = 64 * W;
+  constexpr int I4 = CAP / (4 * T) > 0 ? CAP / (4 * T) : 1;  // 4-slot groups per thread
+  const int nbits = 32 - __clz(n - 1);                        // n >= 2
+  const int nb = 1 << nbits;
+  const int sh = 32 - nbits;
+  for (int i = tid; i <= nb; i += T) L.cnt[i] = 0;
+  team_sync<W>();
+
+  uint32_t kr[I4][4], pos[I4][4];
+  uint32_t live[I4];
+#pragma unroll
+  for (int i = 0; i < I4; ++i) {
+    const int g = T * i + tid;
+    live[i] = 0;
     if (4 * g < n) {
       const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)c, s, 2u * u), k0, k1);
-      *reinterpret_cast<uint4*>(&L.keys[4 * g]) = w;
-    }
-  }
-  const int nbits = 32 - __clz(n - 1);  // n >= 2
-  const int nb = 1 << nbits;
-  for (int i = lane; i <= nb; i += 64) L.cnt[i] = 0;
-  wave_sync();
-
-  uint32_t kr[IT], pos[IT];
-  bool lv[IT];
+      kr[i][0] = w.x;
+      kr[i][1] = w.y;
+      kr[i][2] = w.z;
+      kr[i][3] = w.w;
+      const longlong2 x01 = *reinterpret_cast<const longlong2*>(&L.xs[4 * g]);
+      const longlong2 x23 = *reinterpret_cast<const longlong2*>(&L.xs[4 * g + 2]);
+      const long long xv[4] = {x01.x, x01.y, x23.x, x23.y};
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int j = it * 64 + lane;
-    lv[it] = false;
-    if (it * 64 < n) {
-      lv[it] = j < n && L.xs[j] > 0;
-      if (lv[it]) {
-        kr[it] = L.keys[j];
-        pos[it] = atomicAdd(&L.cnt[kr[it] >> (32 - nbits)], 1u);
+      for (int e = 0; e < 4; ++e) {
+        if (4 * g + e < n && xv[e] > 0) {
+          live[i] |= 1u << e;
+          pos[i][e] = atomicAdd(&L.cnt[kr[i][e] >> sh], 1u);
+        }
       }
     }
   }
-  wave_sync();
-  {  // exclusive scan of the nb bucket counts
-    const int per = nb >= 64 ? nb / 64 : 1;
-    const int first = lane * per;
+  team_sync<W>();
+  {  // exclusive scan of the nb bucket counts over the team
+    const int per = nb >= T ? nb / T : 1;
+    const int first = tid * per;
     int local = 0;
     if (first < nb)
       for (int i = 0; i < per; ++i) local += (int)L.cnt[first + i];
     int run = wave_excl_scan(local, lane);
+    if (W > 1) {
+      if (lane == 63) L.red_i[wv] = run + local;  // this wave's total
+      __syncthreads();
+      for (int k = 0; k < wv; ++k) run += L.red_i[k];
+      __syncthreads();
+    }
     if (first < nb)
       for (int i = 0; i < per; ++i) {
         const int cv = (int)L.cnt[first + i];
         L.cnt[first + i] = (uint32_t)run;
         run += cv;
       }
-    if (lane == 0) L.cnt[nb] = (uint32_t)nlive;
+    if (tid == 0) L.cnt[nb] = (uint32_t)nlive;
   }
-  wave_sync();
+  team_sync<W>();
+  uint32_t st[I4][4], len[I4][4];
+  int maxlen = 0;
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    if (lv[it]) {
-      const int j = it * 64 + lane;
-      L.tmp[L.cnt[kr[it] >> (32 - nbits)] + pos[it]] = (kr[it] << nbits) | (uint32_t)j;
-    }
-  }
-  wave_sync();
+  for (int i = 0; i < I4; ++i)
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    if (lv[it]) {
-      const int j = it * 64 + lane;
-      const uint32_t b = kr[it] >> (32 - nbits);
-      const int st = (int)L.cnt[b], en = (int)L.cnt[b + 1];
-      const uint32_t me = (kr[it] << nbits) | (uint32_t)j;
-      int r = st;
-      for (int qq = st; qq < en; ++qq) r += (L.tmp[qq] < me) ? 1 : 0;
-      L.ord[r] = (uint16_t)j;
+    for (int e = 0; e < 4; ++e) {
+      len[i][e] = 0;
+      if ((live[i] >> e) & 1) {
+        const uint32_t b = kr[i][e] >> sh;
+        st[i][e] = L.cnt[b];
+        len[i][e] = L.cnt[b + 1] - st[i][e];
+        L.tmp[st[i][e] + pos[i][e]] = (kr[i][e] << nbits) | (uint32_t)(4 * (T * i + tid) + e);
+        maxlen = max(maxlen, (int)len[i][e]);
+      }
     }
+  team_sync<W>();
+  // exact rank inside the bucket; all of a thread's buckets advance together
+  uint32_t rk[I4][4];
+#pragma unroll
+  for (int i = 0; i < I4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rk[i][e] = st[i][e];
+  for (int k = 0; k < maxlen; ++k) {
+#pragma unroll
+    for (int i = 0; i < I4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if ((uint32_t)k < len[i][e]) {
+          const uint32_t me = (kr[i][e] << nbits) | (uint32_t)(4 * (T * i + tid) + e);
+          rk[i][e] += (L.tmp[st[i][e] + k] < me) ? 1u : 0u;
+        }
+      }
   }
-  wave_sync();
+  team_sync<W>();
+  uint16_t* perm = perm_of(L);
+#pragma unroll
+  for (int i = 0; i < I4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if ((live[i] >> e) & 1) perm[rk[i][e]] = (uint16_t)(4 * (T * i + tid) + e);
+  team_sync<W>();
 }
 
 enum PassMode { kPassPlain = 0, kPassPmax = 1, kPassAdapt = 2 };
 
-// Candidate pairs of one (sub)step.  kPassPlain updates global memory;
-// kPassPmax stores the pre-products (max xi K) S and returns the largest p at
-// q; kPassAdapt reads them back, clamps p to 1 if asked and updates LDS.
-template <int CAP, int MODE>
-__device__ __forceinline__ double wave_pairs(WaveLds<CAP>& L, const SimDesc* dp, int n, int nlive,
-                                             int lane, int c, uint32_t s, uint32_t u, double q,
-                                             bool clamp, int64_t o0, int* ncoll) {
+// Candidate pairs of one (sub)step; thread h takes sorted positions 4h..4h+3,
+// i.e. pairs 2h and 2h+1, which share one Philox call.  kPassPlain updates
+// global memory; kPassPmax stores the pre-products (max xi K) S and returns
+// this thread's largest p at q; kPassAdapt reads them back, clamps p to 1 if
+// asked and updates LDS.
+template <int CAP, int W, int MODE>
+__device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp, int n,
+                                             int nlive, int tid, int c, uint32_t s, uint32_t u,
+                                             double q, bool clamp, int64_t o0, int* ncoll) {
+  constexpr int T = 64 * W;
+  constexpr int I4 = CAP / (4 * T) > 0 ? CAP / (4 * T) : 1;
   const int P = nlive >> 1;
   const double S = (double)((nlive & 1) ? nlive : nlive - 1);
-  double* pre = reinterpret_cast<double*>(L.tmp);  // CAP/2 doubles fit in tmp
+  double* pre = reinterpret_cast<double*>(L.cnt);  // P <= CAP/2 doubles fit in cnt
+  const uint16_t* perm = perm_of(L);
   double pmax = 0.0;
   const int kind = dp->kernel;
   const double bgol = dp->b;
   int64_t* sink = (MODE == kPassPmax) ? nullptr : dp->sink;
   int64_t sink_base = 0;
   if (sink) sink_base = 2 * dp->pair_base[c];
-  for (int h0 = 0; 2 * h0 < P; h0 += 64) {
-    const int h = h0 + lane;
+#pragma unroll
+  for (int i = 0; i < I4; ++i) {
+    const int h = T * i + tid;
     if (2 * h >= P) continue;
+    const uint2 o4 = *reinterpret_cast<const uint2*>(&perm[4 * h]);
+    const int aa[2] = {(int)(o4.x & 0xFFFFu), (int)(o4.y & 0xFFFFu)};
+    const int bs[2] = {(int)(o4.x >> 16), (int)(o4.y >> 16)};
     uint4 w = make_uint4(0, 0, 0, 0);
     if (MODE != kPassPmax) w = philox(make_uint4((uint32_t)h, (uint32_t)c, s, 2u * u + 1u),
                                       dp->seed_lo, dp->seed_hi);
@@ -287,7 +377,7 @@ __device__ __forceinline__ double wave_pairs(WaveLds<CAP>& L, const SimDesc* dp,
     for (int e = 0; e < 2; ++e) {
       const int m = 2 * h + e;
       if (m >= P) break;
-      const int a = L.ord[2 * m], bb = L.ord[2 * m + 1];
+      const int a = aa[e], bb = bs[e];
       const long long xa = L.xs[a], xb = L.xs[bb];
       const double va = L.vs[a], vb = L.vs[bb];
       double p;
@@ -318,153 +408,170 @@ __device__ __forceinline__ double wave_pairs(WaveLds<CAP>& L, const SimDesc* dp,
         } else {
           update_pair(L.xs, L.vs, a, bb, xa, xb, va, vb, gamma, dp->attrs, dp->n_slots,
                       dp->n_attr, o0 + a, o0 + bb);
-          L.dirty[a] = 1;
-          L.dirty[bb] = 1;
+          atomicOr(&L.dirty[a >> 5], 1u << (a & 31));
+          atomicOr(&L.dirty[bb >> 5], 1u << (bb & 31));
         }
       }
     }
   }
   if (sink && MODE != kPassPmax) {  // unused pair entries of the cell
-    for (int m = P + lane; m < (n >> 1); m += 64) {
+    for (int m = P + tid; m < (n >> 1); m += T) {
       sink[sink_base + 2 * m] = -1;
       sink[sink_base + 2 * m + 1] = -1;
     }
   }
-  wave_sync();
+  team_sync<W>();
   return pmax;
 }
 
-template <int CAP>
-__device__ __forceinline__ int wave_count_live(WaveLds<CAP>& L, int n, int lane) {
+template <int CAP, int W>
+__device__ __forceinline__ int team_count_live(CellLds<CAP>& L, int n, int tid, int lane,
+                                               int wv) {
   int nl = 0;
-  for (int base = 0; base < n; base += 64) {
-    const int j = base + lane;
-    nl += __popcll(__ballot(j < n && L.xs[j] > 0));
-  }
-  return nl;
+  for (int j = tid; j < n; j += 64 * W) nl += L.xs[j] > 0 ? 1 : 0;
+  return team_sum<W>(L, nl, lane, wv);
 }
 
-template <int CAP>
-__global__ void __launch_bounds__(512) k_wave_cells(const SimDesc* __restrict__ descs,
-                                                    const int2* __restrict__ tasks, int n_tasks,
-                                                    uint32_t k_abs) {
-  constexpr int IT = CAP / 64;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int t = blockIdx.x * (blockDim.x >> 6) + wv;
-  if (t >= n_tasks) return;
-  WaveLds<CAP>& L = reinterpret_cast<WaveLds<CAP>*>(smem)[wv];
-  const int2 task = tasks[t];
-  const int sim = __builtin_amdgcn_readfirstlane(task.x);
-  const int c = __builtin_amdgcn_readfirstlane(task.y);
-  const SimDesc* dp = descs + sim;
-  const uint32_t s = k_abs + dp->step_delta;
-  if (s >= dp->step_limit) return;
-  const int64_t o0 = dp->cell_off[c];
-  const int n = (int)(dp->cell_off[c + 1] - o0);
-  const int64_t* gxi = dp->xi + o0;
-  const double* gv = dp->v + o0;
+__device__ __forceinline__ void sink_clear_cell(const SimDesc* dp, int c, int n, int tid, int T) {
+  if (!dp->sink) return;
+  const int64_t base = 2 * dp->pair_base[c];
+  for (int m = tid; m < (n >> 1); m += T) {
+    dp->sink[base + 2 * m] = -1;
+    dp->sink[base + 2 * m + 1] = -1;
+  }
+}
 
-  // stage the cell: all loads first, then the LDS stores
+// Load one cell's xi and v into registers (slot = T it + tid); no waiting.
+template <int CAP, int W>
+__device__ __forceinline__ void fetch_cell(const CellTask& ct, int tid, long long* xr, double* vr) {
+  constexpr int T = 64 * W;
+  constexpr int IT = CAP / T > 0 ? CAP / T : 1;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int j = it * T + tid;
+    if (it * T < ct.n && j < ct.n) {
+      xr[it] = ct.xi[j];
+      vr[it] = ct.v[j];
+    }
+  }
+}
+
+// Persistent cell kernel: workgroup g processes cells g, g + G, g + 2G, ...
+// of the (size-ordered) task list, prefetching the next cell's xi and v into
+// registers while it sorts and pairs the current one.
+template <int CAP, int W, bool ADAPT>
+__global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ descs,
+                                                  const CellTask* __restrict__ tasks,
+                                                  int n_tasks, uint32_t k_abs) {
+  constexpr int T = 64 * W;
+  constexpr int IT = CAP / T > 0 ? CAP / T : 1;
+  __shared__ CellLds<CAP> L;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int G = gridDim.x;
+  int t = blockIdx.x;
+  if (t >= n_tasks) return;
+  CellTask cur = tasks[t];
   long long xr[IT];
   double vr[IT];
+  fetch_cell<CAP, W>(cur, tid, xr, vr);
+  int tn = t + G;
+  CellTask nxt{};
+  if (tn < n_tasks) nxt = tasks[tn];
+  for (;;) {
+    const int c = cur.cell;
+    const int n = cur.n;
+    const SimDesc* dp = descs + cur.sim;
+    const int64_t o0 = cur.xi - dp->xi;
+    const uint32_t s = k_abs + dp->step_delta;
+    const bool active = s < dp->step_limit;
+    // stage the current cell in LDS
+    if (ADAPT)
+      for (int k = tid; k < CAP / 32; k += T) L.dirty[k] = 0;
+    int mylive = 0;
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int j = it * 64 + lane;
-    xr[it] = 0;
-    vr[it] = 0.0;
-    if (it * 64 < n && j < n) {
-      xr[it] = gxi[j];
-      vr[it] = gv[j];
-    }
-  }
-  int nlive = 0;
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    if (it * 64 < n) {
-      const int j = it * 64 + lane;
-      if (j < n) {
+    for (int it = 0; it < IT; ++it) {
+      const int j = it * T + tid;
+      if (it * T < n && j < n) {
         L.xs[j] = xr[it];
         L.vs[j] = vr[it];
-        L.dirty[j] = 0;
+        mylive += xr[it] > 0 ? 1 : 0;
       }
-      nlive += __popcll(__ballot(j < n && xr[it] > 0));
     }
-  }
-  wave_sync();
+    const int nlive = team_sum<W>(L, mylive, lane, wv);  // also orders the LDS stores
+    // prefetch the next cell while this one is processed
+    if (tn < n_tasks) fetch_cell<CAP, W>(nxt, tid, xr, vr);
+    const int tnn = tn + G;
+    CellTask nn{};
+    if (tnn < n_tasks) nn = tasks[tnn];
 
-  int ncoll = 0;
-  int nsub = 1;
-  if (!dp->adaptive) {
-    if (nlive >= 2) {
-      wave_sort(L, n, nlive, lane, c, s, 0u, dp->seed_lo, dp->seed_hi);
-      wave_pairs<CAP, kPassPlain>(L, dp, n, nlive, lane, c, s, 0u, dp->q, false, o0, &ncoll);
-    } else if (dp->sink) {
-      const int64_t base = 2 * dp->pair_base[c];
-      for (int m = lane; m < (n >> 1); m += 64) {
-        dp->sink[base + 2 * m] = -1;
-        dp->sink[base + 2 * m + 1] = -1;
-      }
-    }
-  } else {
-    // per-cell substepping: every p <= 1 (clamped), so gamma <= 1
-    const double dv = dp->dv;
-    double dt_left = dp->dt;
-    uint32_t u = 0;
-    int nl = nlive;
-    const uint32_t umax = (uint32_t)dp->max_substeps;
-    while (dt_left > 0.0 && u < umax) {
-      if (u > 0) nl = wave_count_live(L, n, lane);
-      if (nl < 2) break;
-      wave_sort(L, n, nl, lane, c, s, u, dp->seed_lo, dp->seed_hi);
-      double pmax = wave_pairs<CAP, kPassPmax>(L, dp, n, nl, lane, c, s, u, dt_left / dv, false,
-                                               o0, &ncoll);
-      pmax = wave_max(pmax);
-      const double dt_sub = (pmax <= 1.0) ? dt_left : dt_left / pmax;
-      wave_pairs<CAP, kPassAdapt>(L, dp, n, nl, lane, c, s, u, dt_sub / dv, true, o0, &ncoll);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");  // attribute stores before next reads
-      dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
-      u += 1;
-    }
-    if (dt_left > 0.0 && u >= umax) {  // cap: the rest in one unclamped substep
-      if (lane == 0) atomicOr(dp->status, kFlagSubstepCap);
-      nl = wave_count_live(L, n, lane);
-      if (nl >= 2) {
-        wave_sort(L, n, nl, lane, c, s, u, dp->seed_lo, dp->seed_hi);
-        wave_pairs<CAP, kPassPmax>(L, dp, n, nl, lane, c, s, u, dt_left / dv, false, o0, &ncoll);
-        wave_pairs<CAP, kPassAdapt>(L, dp, n, nl, lane, c, s, u, dt_left / dv, false, o0,
-                                    &ncoll);
-      } else if (dp->sink) {
-        const int64_t base = 2 * dp->pair_base[c];
-        for (int m = lane; m < (n >> 1); m += 64) {
-          dp->sink[base + 2 * m] = -1;
-          dp->sink[base + 2 * m + 1] = -1;
+    if (active) {
+      int ncoll = 0;
+      int nsub = 1;
+      if (!ADAPT) {
+        if (nlive >= 2) {
+          team_sort<CAP, W>(L, n, nlive, tid, lane, wv, c, s, 0u, dp->seed_lo, dp->seed_hi);
+          team_pairs<CAP, W, kPassPlain>(L, dp, n, nlive, tid, c, s, 0u, dp->q, false, o0,
+                                         &ncoll);
+        } else {
+          sink_clear_cell(dp, c, n, tid, T);
+        }
+      } else {
+        // Per-cell substepping: the substep length keeps every p <= 1 (p is
+        // clamped to 1), so gamma <= 1.  After max_substeps substeps the rest
+        // of the step is done in one unclamped substep and SUBSTEP_CAP is set.
+        const double dv = dp->dv;
+        double dt_left = dp->dt;
+        uint32_t u = 0;
+        const uint32_t umax = (uint32_t)dp->max_substeps;
+        while (dt_left > 0.0) {
+          const bool capped = u >= umax;
+          if (capped && tid == 0) atomicOr(dp->status, kFlagSubstepCap);
+          const int nl = u == 0 ? nlive : team_count_live<CAP, W>(L, n, tid, lane, wv);
+          if (nl < 2) {
+            if (capped) {
+              sink_clear_cell(dp, c, n, tid, T);
+              u += 1;
+            }
+            break;
+          }
+          team_sort<CAP, W>(L, n, nl, tid, lane, wv, c, s, u, dp->seed_lo, dp->seed_hi);
+          double pmax = team_pairs<CAP, W, kPassPmax>(L, dp, n, nl, tid, c, s, u, dt_left / dv,
+                                                      false, o0, &ncoll);
+          pmax = team_max<W>(L, pmax, lane, wv);
+          const double dt_sub = (capped || pmax <= 1.0) ? dt_left : dt_left / pmax;
+          team_pairs<CAP, W, kPassAdapt>(L, dp, n, nl, tid, c, s, u, dt_sub / dv, !capped, o0,
+                                         &ncoll);
+          // the next substep's attribute loads come from this same workgroup:
+          // one CU, one vector L1, so ordering the stores first is all it takes
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          team_sync<W>();
+          dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
+          u += 1;
+          if (capped) break;
+        }
+        if (u == 0) sink_clear_cell(dp, c, n, tid, T);
+        nsub = (int)u;
+        team_sync<W>();
+        // write back the slots that changed
+        for (int j = tid; j < n; j += T) {
+          if ((L.dirty[j >> 5] >> (j & 31)) & 1u) {
+            cur.xi[j] = L.xs[j];
+            cur.v[j] = L.vs[j];
+          }
         }
       }
-      u += 1;
+      ncoll = team_sum<W>(L, ncoll, lane, wv);
+      if (tid == 0) add_stats(dp->stats, (unsigned long long)nlive, (unsigned long long)ncoll,
+                              (unsigned long long)nsub);
     }
-    if (u == 0 && dp->sink) {
-      const int64_t base = 2 * dp->pair_base[c];
-      for (int m = lane; m < (n >> 1); m += 64) {
-        dp->sink[base + 2 * m] = -1;
-        dp->sink[base + 2 * m + 1] = -1;
-      }
-    }
-    nsub = (int)u;
-    // write back the slots that changed
-    int64_t* wxi = dp->xi + o0;
-    double* wv2 = dp->v + o0;
-    for (int j = lane; j < n; j += 64) {
-      if (L.dirty[j]) {
-        wxi[j] = L.xs[j];
-        wv2[j] = L.vs[j];
-      }
-    }
+    if (tn >= n_tasks) break;
+    cur = nxt;
+    nxt = nn;
+    tn = tnn;
+    team_sync<W>();  // the LDS of this cell is rewritten next
   }
-  ncoll = wave_sum(ncoll);
-  if (lane == 0) add_stats(dp->stats, (unsigned long long)nlive, (unsigned long long)ncoll,
-                           (unsigned long long)nsub);
 }
 
 // ---------------------------------------------------------------------------
@@ -814,12 +921,12 @@ __global__ void k_kernel_values(int kind, double b, const double* v1, const doub
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-size_t wave_lds_bytes(int cls) {
+size_t cell_lds_bytes(int cls) {
   switch (cls) {
-    case 0: return sizeof(WaveLds<64>);
-    case 1: return sizeof(WaveLds<128>);
-    case 2: return sizeof(WaveLds<256>);
-    default: return sizeof(WaveLds<512>);
+    case 0: return sizeof(CellLds<64>);
+    case 1: return sizeof(CellLds<128>);
+    case 2: return sizeof(CellLds<256>);
+    default: return sizeof(CellLds<512>);
   }
 }
 
@@ -827,35 +934,57 @@ void set_lds_limits() {
   static bool done = false;
   if (done) return;
   done = true;
-  const int lim = 160 * 1024;
-  (void)hipFuncSetAttribute((const void*)k_wave_cells<64>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  (void)hipFuncSetAttribute((const void*)k_wave_cells<128>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  (void)hipFuncSetAttribute((const void*)k_wave_cells<256>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  (void)hipFuncSetAttribute((const void*)k_wave_cells<512>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void*)k_big_rank, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lim);
+                            160 * 1024);
   (void)hipGetLastError();
 }
 
-template <int CAP>
-static void launch_class(const PlanDev& p, int cls, uint32_t k_abs, int wpb, hipStream_t st) {
-  const int n = p.n_wave[cls];
-  if (n <= 0) return;
-  const int grid = (n + wpb - 1) / wpb;
-  hipLaunchKernelGGL(k_wave_cells<CAP>, dim3(grid), dim3(64 * wpb),
-                     (unsigned)(wpb * sizeof(WaveLds<CAP>)), st, p.desc, p.wave_tasks[cls], n,
-                     k_abs);
+// resident workgroups of one cell kernel on this device (cached per instantiation)
+template <int CAP, int W, bool ADAPT>
+static int persistent_grid() {
+  static int grid = 0;
+  if (grid == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cells<CAP, W, ADAPT>, 64 * W, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 1;
+    (void)hipGetLastError();
+    grid = per_cu * cus;
+  }
+  return grid;
 }
 
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int wpb, hipStream_t st) {
-  launch_class<512>(p, 3, k_abs, wpb, st);
-  launch_class<256>(p, 2, k_abs, wpb, st);
-  launch_class<128>(p, 1, k_abs, wpb, st);
-  launch_class<64>(p, 0, k_abs, wpb, st);
+template <int CAP, int W>
+static void launch_class_w(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st) {
+  const int np = p.n_plain[cls], na = p.n_wave[cls] - p.n_plain[cls];
+  if (np > 0)
+    hipLaunchKernelGGL((k_cells<CAP, W, false>), dim3(std::min(np, persistent_grid<CAP, W, false>())),
+                       dim3(64 * W), 0, st, p.desc, p.wave_tasks[cls], np, k_abs);
+  if (na > 0)
+    hipLaunchKernelGGL((k_cells<CAP, W, true>), dim3(std::min(na, persistent_grid<CAP, W, true>())),
+                       dim3(64 * W), 0, st, p.desc, p.wave_tasks[cls] + np, na, k_abs);
+}
+
+template <int CAP>
+static void launch_class(const PlanDev& p, int cls, uint32_t k_abs, int w, hipStream_t st) {
+  switch (w) {
+    case 1: launch_class_w<CAP, 1>(p, cls, k_abs, st); break;
+    case 2: launch_class_w<CAP, 2>(p, cls, k_abs, st); break;
+    case 4: launch_class_w<CAP, 4>(p, cls, k_abs, st); break;
+    default: launch_class_w<CAP, 8>(p, cls, k_abs, st); break;
+  }
+}
+
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st) {
+  launch_class<512>(p, 3, k_abs, waves_per_cell, st);
+  launch_class<256>(p, 2, k_abs, waves_per_cell, st);
+  launch_class<128>(p, 1, k_abs, waves_per_cell, st);
+  launch_class<64>(p, 0, k_abs, waves_per_cell, st);
   if (p.n_big > 0) {
     hipLaunchKernelGGL(k_big_count, dim3(p.n_chunks), dim3(256), 0, st, p.desc, p.big, p.chunks,
                        p.bucket_cnt, p.task_live, k_abs);

@@ -115,9 +115,9 @@ def test_golovin_random_cells(B, orc, max_sd, seed, n_attr, boost):
 
 def test_golovin_tunings_same_result(B, orc):
     st = I.random_cells(64, 900, n_attr=1, rng_seed=9, p_boost=100.0)
-    for tu in [dict(wave_class_mask=8, waves_per_block=1, big_bucket_target=32),
-               dict(wave_class_mask=15, waves_per_block=8, big_bucket_target=1024),
-               dict(wave_class_mask=10, waves_per_block=2, big_bucket_target=128)]:
+    for tu in [dict(wave_class_mask=8, waves_per_cell=1, big_bucket_target=32),
+               dict(wave_class_mask=15, waves_per_cell=8, big_bucket_target=1024),
+               dict(wave_class_mask=10, waves_per_cell=2, big_bucket_target=128)]:
         say(f"tuning {tu}")
         assert _compare_run(B, orc, st, 6, tuning=tu, label=str(tu))
 
