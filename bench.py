@@ -104,11 +104,18 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="grid256",
-                    choices=["grid256", "grid64", "golovin", "geometric"])
+                    choices=["grid256", "grid64", "golovin", "geometric", "serving"])
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cells", type=int, default=4096)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-cells", type=int, default=65536)
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="before timing, copy a buffer of this size 3 times (a plain copy "
+                         "kernel of known traffic, to scale rocprofv3 FETCH/WRITE_SIZE)")
+    ap.add_argument("--serve-requests", type=int, default=1024)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-baseline", type=int, default=128,
+                    help="requests replayed one at a time for the baseline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -124,6 +131,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe_gib > 0:
+        n = int(args.copy_probe_gib * 2 ** 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload == "serving":
+        return serve_bench(args)
     state, workload = make_state(args.workload)
     host_state = state.copy()
     sim = B.Sim(state)
@@ -183,9 +200,10 @@ def main():
                  + 8 * state.n_cells * K)
     value = live / (total_ms / 1e3)
     single_launch = args.workload in ("grid256", "grid64")
-    kernel_name = "k_wave_cells_512" if single_launch else "whole_step"
+    kernel_name = (f"k_cells<512,{tuning['waves_per_cell']},{'adaptive' if state.adaptive else 'plain'}>"
+                   if single_launch else "whole_step")
     achieved = alg_bytes / K / (per_launch_ms.mean() / 1e3) / 1e9
-    traffic = traffic_from_profiles(kernel_name, args.workload, alg_bytes / K)
+    traffic = traffic_from_profiles("k_cells", args.workload, alg_bytes / K)
     line = {
         "metric": METRIC,
         "value": value,
@@ -230,6 +248,62 @@ def main():
         line["cpu_baseline"] = cpu_baseline(host_state, args.cpu_cells, args.cpu_steps)
     else:
         line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+def serve_bench(args):
+    """Continuous batching of box requests (Poisson arrivals) against the
+    one-at-a-time baseline on a prefix of the same trace."""
+    import torch
+
+    from paper_2103_17238_amd import inputs as I
+    from paper_2103_17238_amd.serving import GpuExecutor, Server, serve_one_at_a_time
+
+    reqs = I.serving_requests(args.serve_requests, rate_per_s=args.serve_rate)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    ex = GpuExecutor()
+    srv = Server(ex, budget_bytes=budget, steps_per_tick=25)
+    # warm-up: kernels compiled / loaded, allocator primed
+    Server(GpuExecutor(), budget_bytes=budget, steps_per_tick=25).run(reqs[:8], I.request_state)
+    stats = srv.run(reqs, I.request_state)
+    ex.close()
+    served = stats.summary()
+    base_reqs = reqs[: args.serve_baseline]
+    bstats = serve_one_at_a_time(base_reqs, I.request_state, GpuExecutor())
+    base = bstats.summary()
+    alg = 16 * served["sd_steps"]
+    line = {
+        "metric": METRIC,
+        "value": served["sd_steps_per_s"],
+        "unit": "SD-steps/s",
+        "n_gpus": 1,
+        "steps": args.serve_requests,
+        "warmup": 8,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (Poisson arrivals, log-uniform SD counts, seeded)",
+        "config": {
+            "workload": f"serving_{args.serve_requests}_requests_{args.serve_rate:g}_per_s_"
+                        "nsd_2^10..2^16_600_steps",
+            "parallelism": "1 GPU, continuous batching, one shared launch per step",
+            "budget_bytes": budget,
+            "steps_per_tick": 25,
+        },
+        "serving": served,
+        "one_at_a_time": dict(base, requests=len(base_reqs)),
+        "roofline": {
+            "bound": "hbm", "kernel": "whole_step", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "achieved": alg / stats.device_busy_s / 1e9 if stats.device_busy_s else None,
+            "frac": alg / stats.device_busy_s / 1e9 / HBM_PEAK_GBS if stats.device_busy_s
+            else None,
+            "traffic": None, "note": "16 B per live SD-step over device-busy time",
+        },
+        "cpu_baseline": None,
+    }
     print(json.dumps(line), flush=True)
 
 

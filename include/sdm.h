@@ -95,8 +95,12 @@ typedef struct {
                                 workgroup-per-cell launch; cells go to the smallest enabled
                                 class that fits; bit 3 (512) is always on */
   int32_t waves_per_cell;    /* 1, 2, 4 or 8: wavefronts in the workgroup of one cell */
-  int32_t big_bucket_target; /* cells > 512 slots: expected SDs per sort bucket, 32..1024 */
+  int32_t big_bucket_target; /* cells on the big-cell path: expected SDs per sort bucket,
+                                32..1024 */
   int32_t lpt_order;         /* 1: dispatch cells by descending size */
+  int32_t mid_max_slots;     /* cells of 513..mid_max_slots slots (<= 16384) get one workgroup
+                                each (mid-size kernel); larger ones take the multi-pass
+                                big-cell path; 0 sends every cell above 512 there */
 } sdm_tuning;
 
 /*
@@ -113,7 +117,7 @@ size_t sdm_workspace_bytes(const sdm_config* cfg, const int64_t* host_cell_off);
  * to the host, validates cfg and the state (one kernel, then a stream
  * synchronisation), and plans the launches.  The step counter starts at 0.
  * Returns SDM_EINVAL for a bad cfg/state (also: adaptive mode with a cell of
- * more than 512 slots), SDM_ENOMEM if the workspace is too small.
+ * more than 16384 slots), SDM_ENOMEM if the workspace is too small.
  */
 sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v, double* attrs,
                     const int64_t* cell_off, void* workspace, size_t workspace_bytes,

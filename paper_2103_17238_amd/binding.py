@@ -54,6 +54,7 @@ class sdm_tuning(C.Structure):
         ("waves_per_cell", C.c_int32),
         ("big_bucket_target", C.c_int32),
         ("lpt_order", C.c_int32),
+        ("mid_max_slots", C.c_int32),
     ]
 
     def as_dict(self):

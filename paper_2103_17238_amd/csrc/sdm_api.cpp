@@ -44,13 +44,15 @@ sdm_tuning default_tuning() {
   t.waves_per_cell = 1;
   t.big_bucket_target = 256;
   t.lpt_order = 1;
+  t.mid_max_slots = sdm::kMidCapMax;
   return t;
 }
 
 bool tuning_ok(const sdm_tuning& t) {
   const int w = t.waves_per_cell;
   return (w == 1 || w == 2 || w == 4 || w == 8) && t.big_bucket_target >= sdm::kMinBucketTarget &&
-         t.big_bucket_target <= 1024 && (t.wave_class_mask & ~0xF) == 0;
+         t.big_bucket_target <= 1024 && (t.wave_class_mask & ~0xF) == 0 &&
+         t.mid_max_slots >= 0 && t.mid_max_slots <= sdm::kMidCapMax;
 }
 
 }  // namespace
@@ -83,6 +85,9 @@ struct sdm_sim {
 struct Tables {
   std::vector<sdm::CellTask> wave[sdm::kNumClasses];  // plain-mode cells first, then adaptive
   int n_plain[sdm::kNumClasses] = {0, 0, 0, 0};
+  std::vector<sdm::CellTask> mid[sdm::kNumMid];  // plain-mode cells first, then adaptive
+  int n_mid_plain[sdm::kNumMid] = {0, 0, 0, 0};
+  bool adaptive_big = false;  // an adaptive-mode cell fell to the big-cell path
   std::vector<BigTask> big;
   std::vector<BigChunk> chunks;
   std::vector<BigBucket> buckets;
@@ -102,6 +107,7 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
     int sim, cell, adaptive;
   };
   std::vector<Item> items[sdm::kNumClasses];
+  std::vector<Item> mids[sdm::kNumMid];
   const int mask = tu.wave_class_mask | 0x8;
   for (int i = 0; i < (int)ms.size(); ++i) {
     const auto& off = ms[i]->off;
@@ -115,6 +121,13 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
         items[k].push_back({n, i, c, ms[i]->cfg.adaptive});
         continue;
       }
+      if (n <= tu.mid_max_slots) {
+        int k = 0;
+        while (n > sdm::mid_cap(k)) ++k;
+        mids[k].push_back({n, i, c, ms[i]->cfg.adaptive});
+        continue;
+      }
+      if (ms[i]->cfg.adaptive) T.adaptive_big = true;
       BigTask t{};
       t.sim = i;
       t.cell = c;
@@ -134,18 +147,18 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
       for (int64_t g = 0; g < groups; g += 256) T.pblocks.push_back({ti, (int32_t)g});
     }
   }
-  for (int k = 0; k < sdm::kNumClasses; ++k) {
-    auto& v = items[k];
+  // plain-mode cells first (one kernel each), largest first within a mode
+  auto order = [&](std::vector<Item>& v, std::vector<sdm::CellTask>& out, int& n_plain) {
     std::stable_sort(v.begin(), v.end(), [&](const Item& a, const Item& b) {
       if (a.adaptive != b.adaptive) return a.adaptive < b.adaptive;
       return tu.lpt_order ? a.n > b.n : false;
     });
-    T.n_plain[k] = 0;
-    for (auto& it : v) T.n_plain[k] += it.adaptive ? 0 : 1;
-    T.wave[k].resize(v.size());
+    n_plain = 0;
+    for (auto& it : v) n_plain += it.adaptive ? 0 : 1;
+    out.resize(v.size());
     for (size_t j = 0; j < v.size(); ++j) {
       const sdm_sim* m = ms[v[j].sim];
-      sdm::CellTask& ct = T.wave[k][j];
+      sdm::CellTask& ct = out[j];
       ct.xi = m->xi + m->off[v[j].cell];
       ct.v = m->v + m->off[v[j].cell];
       ct.n = (int32_t)v[j].n;
@@ -153,11 +166,13 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
       ct.cell = v[j].cell;
       ct.pad = 0;
     }
-  }
+  };
+  for (int k = 0; k < sdm::kNumClasses; ++k) order(items[k], T.wave[k], T.n_plain[k]);
+  for (int k = 0; k < sdm::kNumMid; ++k) order(mids[k], T.mid[k], T.n_mid_plain[k]);
 }
 
 struct Layout {
-  size_t desc, wave[sdm::kNumClasses], big, chunks, buckets, pblocks, bucket_cnt, bucket_start,
+  size_t desc, wave[sdm::kNumClasses], mid[sdm::kNumMid], big, chunks, buckets, pblocks, bucket_cnt, bucket_start,
       task_live, task_nlive, tmp, ord, total;
 };
 
@@ -172,6 +187,8 @@ static Layout layout_of(int n_members, const Tables& T) {
   L.desc = take(sizeof(SimDesc) * std::max(n_members, 1));
   for (int k = 0; k < sdm::kNumClasses; ++k)
     L.wave[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(T.wave[k].size(), 1));
+  for (int k = 0; k < sdm::kNumMid; ++k)
+    L.mid[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(T.mid[k].size(), 1));
   L.big = take(sizeof(BigTask) * std::max<size_t>(T.big.size(), 1));
   L.chunks = take(sizeof(BigChunk) * std::max<size_t>(T.chunks.size(), 1));
   L.buckets = take(sizeof(BigBucket) * std::max<size_t>(T.buckets.size(), 1));
@@ -186,14 +203,23 @@ static Layout layout_of(int n_members, const Tables& T) {
   return L;
 }
 
-// plan bytes for the worst-case tuning (smallest bucket target, all classes)
+// plan bytes for the worst-case tuning: every cell above 512 slots may go to
+// the big-cell path (smallest bucket target) or to a mid-size list, and the
+// class masks split the same cells differently (one alignment pad per list)
 static size_t plan_bytes_worst(const std::vector<sdm_sim*>& ms) {
   sdm_tuning t = default_tuning();
   t.big_bucket_target = sdm::kMinBucketTarget;
+  t.mid_max_slots = 0;
   Tables T;
   build_tables(ms, t, T);
-  // other class masks split the same cells differently: one alignment pad per class
-  return layout_of((int)ms.size(), T).total + sdm::kNumClasses * kAlign;
+  size_t n_mid = 0;
+  for (auto* s : ms)
+    for (int c = 0; c < s->cfg.n_cells; ++c) {
+      const int64_t n = s->off[c + 1] - s->off[c];
+      n_mid += (n > sdm::kWaveCapMax && n <= sdm::kMidCapMax) ? 1 : 0;
+    }
+  return layout_of((int)ms.size(), T).total + align_up(sizeof(sdm::CellTask) * n_mid) +
+         (sdm::kNumClasses + sdm::kNumMid) * kAlign;
 }
 
 struct Plan {
@@ -262,8 +288,11 @@ static size_t lds_block_limit() {
 static sdm_status plan_setup(Plan* p, hipStream_t st) {
   p->T = Tables();
   build_tables(p->members, p->tuning, p->T);
+  if (p->T.adaptive_big) return SDM_EINVAL;  // adaptive mode needs cells <= mid_max_slots
   for (int k = 0; k < sdm::kNumClasses; ++k)  // every used class must fit one workgroup's LDS
     if (!p->T.wave[k].empty() && sdm::cell_lds_bytes(k) > lds_block_limit()) return SDM_EINVAL;
+  for (int k = 0; k < sdm::kNumMid; ++k)
+    if (!p->T.mid[k].empty() && sdm::mid_lds_bytes(k) > lds_block_limit()) return SDM_EINVAL;
   const Layout L = layout_of((int)p->members.size(), p->T);
   if (L.total > p->ws_bytes) return SDM_ENOMEM;
   char* w = p->ws;
@@ -275,6 +304,11 @@ static sdm_status plan_setup(Plan* p, hipStream_t st) {
     d.wave_tasks[k] = reinterpret_cast<const sdm::CellTask*>(w + L.wave[k]);
     d.n_wave[k] = (int)p->T.wave[k].size();
     d.n_plain[k] = p->T.n_plain[k];
+  }
+  for (int k = 0; k < sdm::kNumMid; ++k) {
+    d.mid_tasks[k] = reinterpret_cast<const sdm::CellTask*>(w + L.mid[k]);
+    d.n_mid[k] = (int)p->T.mid[k].size();
+    d.n_mid_plain[k] = p->T.n_mid_plain[k];
   }
   d.big = reinterpret_cast<const BigTask*>(w + L.big);
   d.n_big = (int)p->T.big.size();
@@ -297,6 +331,8 @@ static sdm_status plan_setup(Plan* p, hipStream_t st) {
   HIP_TRY(upload(const_cast<SimDesc*>(d.desc), p->desc));
   for (int k = 0; k < sdm::kNumClasses; ++k)
     HIP_TRY(upload(const_cast<sdm::CellTask*>(d.wave_tasks[k]), p->T.wave[k]));
+  for (int k = 0; k < sdm::kNumMid; ++k)
+    HIP_TRY(upload(const_cast<sdm::CellTask*>(d.mid_tasks[k]), p->T.mid[k]));
   HIP_TRY(upload(const_cast<BigTask*>(d.big), p->T.big));
   HIP_TRY(upload(const_cast<BigChunk*>(d.chunks), p->T.chunks));
   HIP_TRY(upload(const_cast<BigBucket*>(d.buckets), p->T.buckets));
@@ -394,7 +430,7 @@ static size_t plan_bytes_bound(const sdm_config* c) {
   size_t o = 0;
   auto take = [&](size_t b) { o += align_up(b); };
   take(sizeof(SimDesc));
-  for (int k = 0; k < sdm::kNumClasses; ++k)
+  for (int k = 0; k < sdm::kNumClasses + sdm::kNumMid; ++k)
     take(sizeof(sdm::CellTask) * (size_t)std::max<int64_t>(C, 1));
   take(sizeof(BigTask) * (size_t)std::max<int64_t>(nbig, 1));
   take(sizeof(BigChunk) * (size_t)(ns / sdm::kChunk + nbig + 1));
@@ -457,7 +493,7 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
   }
   if (cfg->adaptive) {
     for (int c = 0; c < cfg->n_cells; ++c)
-      if (s->off[c + 1] - s->off[c] > sdm::kWaveCapMax) {
+      if (s->off[c + 1] - s->off[c] > sdm::kMidCapMax) {
         delete s;
         return SDM_EINVAL;
       }
@@ -733,9 +769,10 @@ static bool cache_lookup(const char* path, const std::string& key, sdm_tuning* t
     double ms = 0;
     if (std::sscanf(line,
                     "{\"key\": \"%511[^\"]\", \"wave_class_mask\": %d, \"waves_per_cell\": %d, "
-                    "\"big_bucket_target\": %d, \"lpt_order\": %d, \"ms_per_step\": %lf}",
+                    "\"big_bucket_target\": %d, \"lpt_order\": %d, \"mid_max_slots\": %d, "
+                    "\"ms_per_step\": %lf}",
                     k, &x.wave_class_mask, &x.waves_per_cell, &x.big_bucket_target,
-                    &x.lpt_order, &ms) == 6 &&
+                    &x.lpt_order, &x.mid_max_slots, &ms) == 7 &&
         key == k && tuning_ok(x)) {
       *t = x;  // the last matching line wins
       found = true;
@@ -750,9 +787,10 @@ static void cache_store(const char* path, const std::string& key, const sdm_tuni
   if (!f) return;
   std::fprintf(f,
                "{\"key\": \"%s\", \"wave_class_mask\": %d, \"waves_per_cell\": %d, "
-               "\"big_bucket_target\": %d, \"lpt_order\": %d, \"ms_per_step\": %.6f}\n",
+               "\"big_bucket_target\": %d, \"lpt_order\": %d, \"mid_max_slots\": %d, "
+               "\"ms_per_step\": %.6f}\n",
                key.c_str(), t.wave_class_mask, t.waves_per_cell, t.big_bucket_target,
-               t.lpt_order, ms);
+               t.lpt_order, t.mid_max_slots, ms);
   std::fclose(f);
 }
 
@@ -798,10 +836,11 @@ extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_byt
   };
 
   // candidate shapes
-  bool has_small[4] = {false, false, false, false}, has_big = false;
+  bool has_small[4] = {false, false, false, false}, has_big = false, has_mid = false;
   for (int c = 0; c < s->cfg.n_cells; ++c) {
     const int64_t n = s->off[c + 1] - s->off[c];
-    if (n > sdm::kWaveCapMax) has_big = true;
+    if (n > sdm::kMidCapMax) has_big = true;
+    else if (n > sdm::kWaveCapMax) has_mid = true;
     else if (n > 0) has_small[n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3] = true;
   }
   std::vector<int> masks = {0x8};
@@ -811,11 +850,21 @@ extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_byt
       if (((m >> k) & 1) && has_small[k]) useful = true;
     if (useful) masks.push_back(m);
   }
-  std::vector<int> targets = has_big ? std::vector<int>{64, 128, 256, 512} : std::vector<int>{256};
+  std::vector<int> mids = has_mid && !s->cfg.adaptive ? std::vector<int>{sdm::kMidCapMax, 0}
+                                                      : std::vector<int>{sdm::kMidCapMax};
   std::vector<sdm_tuning> cands;
-  for (int m : masks)
-    for (int wpb : {1, 2, 4, 8})
-      for (int tg : targets) cands.push_back({m, wpb, tg, 1});
+  for (int mm : mids) {
+    // the bucket size matters only when some cell takes the big-cell path
+    const bool bigs = has_big || (mm == 0 && has_mid);
+    const std::vector<int> targets =
+        bigs ? std::vector<int>{64, 128, 256, 512} : std::vector<int>{256};
+    const std::vector<int> waves = has_small[0] || has_small[1] || has_small[2] || has_small[3]
+                                       ? std::vector<int>{1, 2, 4, 8}
+                                       : std::vector<int>{1};
+    for (int m : masks)
+      for (int wpb : waves)
+        for (int tg : targets) cands.push_back({m, wpb, tg, 1, mm});
+  }
 
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));

@@ -10,7 +10,9 @@ namespace sdm {
 constexpr int kStatSlots = 256;   // spread of the statistics counters (fewer atomics per address)
 constexpr int kStatFields = 4;    // live SD-steps, colliding pairs, cell substeps, cell steps
 constexpr int kNumClasses = 4;    // workgroup-per-cell capacities 64, 128, 256, 512 slots
-constexpr int kWaveCapMax = 512;  // cells above this go to the big-cell path
+constexpr int kWaveCapMax = 512;  // cells above this go to the mid-size or big-cell path
+constexpr int kNumMid = 4;        // mid-size capacities 2048, 4096, 8192, 16384 slots
+constexpr int kMidCapMax = 16384;
 constexpr int kChunk = 1024;      // slots per block in the big-cell key passes
 constexpr int kBucketCap = 1024;  // big-cell bucket entries staged in LDS by one wave
 constexpr int kMinBucketTarget = 32;
@@ -21,6 +23,7 @@ constexpr uint32_t kFlagBucketOverflow = 4u;
 constexpr uint32_t kFlagInvalid = 8u;
 
 inline int class_cap(int k) { return 64 << k; }
+inline int mid_cap(int k) { return 2048 << k; }
 
 // Per-simulation parameters read by every step kernel (device array, one per member).
 struct SimDesc {
@@ -90,6 +93,9 @@ struct PlanDev {
   const CellTask* wave_tasks[kNumClasses];  // per class: plain-mode cells first, then adaptive
   int n_wave[kNumClasses];
   int n_plain[kNumClasses];
+  const CellTask* mid_tasks[kNumMid];  // per mid class: plain-mode cells first
+  int n_mid[kNumMid];
+  int n_mid_plain[kNumMid];
   const BigTask* big;
   int n_big;
   const BigChunk* chunks;
@@ -118,6 +124,7 @@ hipError_t launch_philox_fill(uint32_t* out, int64_t n, uint32_t c0, uint32_t c1
 hipError_t launch_kernel_values(int kind, double b, const double* v1, const double* v2, int64_t n,
                                 double* out, hipStream_t st);
 size_t cell_lds_bytes(int cls);
+size_t mid_lds_bytes(int cls);
 void set_lds_limits();
 
 }  // namespace sdm

@@ -67,10 +67,12 @@ constexpr double kU2 = 8.0e3;
 constexpr double kU3 = 201.0;
 
 __device__ __forceinline__ double fall_speed(double r) {
-  const double u1 = kU1 * r * r;
-  const double u2 = kU2 * r;
-  const double u3 = kU3 * sqrt(r);
-  return fmin(fmin(u1, u2), u3);
+  const double u12 = fmin(kU1 * r * r, kU2 * r);
+  // Up to 600 um the square-root regime lies at least 2.6 % above the linear
+  // one (it crosses at (k3/k2)^2 = 631 um), so it cannot be the minimum and
+  // its square root is skipped: the result is the same bits.
+  if (r <= 6.0e-4) return u12;
+  return fmin(u12, kU3 * sqrt(r));
 }
 
 __device__ __forceinline__ double coal_kernel(int kind, double b, double va, double vb) {
@@ -82,6 +84,7 @@ __device__ __forceinline__ double coal_kernel(int kind, double b, double va, dou
 }
 
 __device__ __forceinline__ long long collisions(double p, double phi, uint32_t* status) {
+  if (p < 1.0) return phi < p ? 1 : 0;  // floor(p) = 0 and p - floor(p) = p
   if (!(p < 0x1p62)) {
     atomicOr(status, kFlagGammaCap);
     return 1LL << 62;
@@ -175,6 +178,42 @@ __device__ __forceinline__ void update_pair(XI* xs, VV* vs, int ia, int ib, long
   }
 }
 
+// A thread's share of the bucket-counter scan: `per` consecutive counters
+// from `first` (16-byte LDS accesses when per is a multiple of 4).
+__device__ __forceinline__ int scan_load(const uint32_t* cnt, int first, int per, int nb) {
+  int local = 0;
+  if (first >= nb) return 0;
+  if ((per & 3) == 0) {
+    for (int i = 0; i < per; i += 4) {
+      const uint4 q = *reinterpret_cast<const uint4*>(&cnt[first + i]);
+      local += (int)(q.x + q.y + q.z + q.w);
+    }
+  } else {
+    for (int i = 0; i < per; ++i) local += (int)cnt[first + i];
+  }
+  return local;
+}
+
+// replace the counters by their exclusive prefix sums starting at `run`
+__device__ __forceinline__ void scan_store(uint32_t* cnt, int first, int per, int nb, int run) {
+  if (first >= nb) return;
+  if ((per & 3) == 0) {
+    for (int i = 0; i < per; i += 4) {
+      uint4 q = *reinterpret_cast<const uint4*>(&cnt[first + i]);
+      const uint32_t a = (uint32_t)run, b = a + q.x, c2 = b + q.y, d = c2 + q.z;
+      run = (int)(d + q.w);
+      q = make_uint4(a, b, c2, d);
+      *reinterpret_cast<uint4*>(&cnt[first + i]) = q;
+    }
+  } else {
+    for (int i = 0; i < per; ++i) {
+      const int cv = (int)cnt[first + i];
+      cnt[first + i] = (uint32_t)run;
+      run += cv;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One workgroup ("team" of W wavefronts) per cell of <= CAP slots.
 //
@@ -188,7 +227,7 @@ __device__ __forceinline__ void update_pair(XI* xs, VV* vs, int ia, int ib, long
 // Philox call, so keys never go through LDS.
 // ---------------------------------------------------------------------------
 template <int CAP>
-struct CellLds {
+struct alignas(16) CellLds {
   long long xs[CAP];  // multiplicities (slot order)
   double vs[CAP];     // volumes (slot order)
   uint32_t tmp[CAP];  // bucketed (key << nbits | slot), then uint16 permutation
@@ -206,30 +245,41 @@ __device__ __forceinline__ void team_sync() {
     __syncthreads();
 }
 
-template <int W, int CAP>
-__device__ __forceinline__ int team_sum(CellLds<CAP>& L, int x, int lane, int wv) {
+// team-wide sum / max; red points to >= W LDS slots
+template <int W>
+__device__ __forceinline__ int team_sum_r(int* red, int x, int lane, int wv) {
   x = wave_sum(x);
   if (W == 1) return x;
-  if (lane == 0) L.red_i[wv] = x;
+  if (lane == 0) red[wv] = x;
   __syncthreads();
   int t = 0;
 #pragma unroll
-  for (int k = 0; k < W; ++k) t += L.red_i[k];
+  for (int k = 0; k < W; ++k) t += red[k];
+  __syncthreads();
+  return t;
+}
+
+template <int W>
+__device__ __forceinline__ double team_max_r(double* red, double x, int lane, int wv) {
+  x = wave_max(x);
+  if (W == 1) return x;
+  if (lane == 0) red[wv] = x;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) t = fmax(t, red[k]);
   __syncthreads();
   return t;
 }
 
 template <int W, int CAP>
+__device__ __forceinline__ int team_sum(CellLds<CAP>& L, int x, int lane, int wv) {
+  return team_sum_r<W>(L.red_i, x, lane, wv);
+}
+
+template <int W, int CAP>
 __device__ __forceinline__ double team_max(CellLds<CAP>& L, double x, int lane, int wv) {
-  x = wave_max(x);
-  if (W == 1) return x;
-  if (lane == 0) L.red_d[wv] = x;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int k = 0; k < W; ++k) t = fmax(t, L.red_d[k]);
-  __syncthreads();
-  return t;
+  return team_max_r<W>(L.red_d, x, lane, wv);
 }
 
 template <int CAP>
@@ -247,7 +297,8 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
   const int nbits = 32 - __clz(n - 1);                        // n >= 2
   const int nb = 1 << nbits;
   const int sh = 32 - nbits;
-  for (int i = tid; i <= nb; i += T) L.cnt[i] = 0;
+  for (int i = 4 * tid; i < nb + 4; i += 4 * T)  // counters 0..nb, 16 bytes at a time
+    *reinterpret_cast<uint4*>(&L.cnt[i]) = make_uint4(0u, 0u, 0u, 0u);
   team_sync<W>();
 
   uint32_t kr[I4][4], pos[I4][4];
@@ -278,9 +329,7 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
   {  // exclusive scan of the nb bucket counts over the team
     const int per = nb >= T ? nb / T : 1;
     const int first = tid * per;
-    int local = 0;
-    if (first < nb)
-      for (int i = 0; i < per; ++i) local += (int)L.cnt[first + i];
+    int local = scan_load(L.cnt, first, per, nb);
     int run = wave_excl_scan(local, lane);
     if (W > 1) {
       if (lane == 63) L.red_i[wv] = run + local;  // this wave's total
@@ -288,12 +337,7 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
       for (int k = 0; k < wv; ++k) run += L.red_i[k];
       __syncthreads();
     }
-    if (first < nb)
-      for (int i = 0; i < per; ++i) {
-        const int cv = (int)L.cnt[first + i];
-        L.cnt[first + i] = (uint32_t)run;
-        run += cv;
-      }
+    scan_store(L.cnt, first, per, nb, run);
     if (tid == 0) L.cnt[nb] = (uint32_t)nlive;
   }
   team_sync<W>();
@@ -441,141 +485,367 @@ __device__ __forceinline__ void sink_clear_cell(const SimDesc* dp, int c, int n,
   }
 }
 
-// Load one cell's xi and v into registers (slot = T it + tid); no waiting.
-template <int CAP, int W>
-__device__ __forceinline__ void fetch_cell(const CellTask& ct, int tid, long long* xr, double* vr) {
-  constexpr int T = 64 * W;
-  constexpr int IT = CAP / T > 0 ? CAP / T : 1;
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int j = it * T + tid;
-    if (it * T < ct.n && j < ct.n) {
-      xr[it] = ct.xi[j];
-      vr[it] = ct.v[j];
-    }
-  }
-}
-
-// Persistent cell kernel: workgroup g processes cells g, g + G, g + 2G, ...
-// of the (size-ordered) task list, prefetching the next cell's xi and v into
-// registers while it sorts and pairs the current one.
+// One workgroup per cell of the (size-ordered) task list.  The task entry
+// carries the cell's data pointers, so the loads of xi and v depend on one
+// lookup only; the hardware dispatcher starts the next cell's workgroup as
+// soon as one finishes (largest cells first).
 template <int CAP, int W, bool ADAPT>
 __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ descs,
                                                   const CellTask* __restrict__ tasks,
-                                                  int n_tasks, uint32_t k_abs) {
+                                                  uint32_t k_abs) {
   constexpr int T = 64 * W;
   constexpr int IT = CAP / T > 0 ? CAP / T : 1;
   __shared__ CellLds<CAP> L;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int G = gridDim.x;
-  int t = blockIdx.x;
-  if (t >= n_tasks) return;
-  CellTask cur = tasks[t];
+  const CellTask cur = tasks[blockIdx.x];
+  const int n = cur.n;
+  // all loads first (coalesced, slot = T it + tid)
   long long xr[IT];
   double vr[IT];
-  fetch_cell<CAP, W>(cur, tid, xr, vr);
-  int tn = t + G;
-  CellTask nxt{};
-  if (tn < n_tasks) nxt = tasks[tn];
-  for (;;) {
-    const int c = cur.cell;
-    const int n = cur.n;
-    const SimDesc* dp = descs + cur.sim;
-    const int64_t o0 = cur.xi - dp->xi;
-    const uint32_t s = k_abs + dp->step_delta;
-    const bool active = s < dp->step_limit;
-    // stage the current cell in LDS
-    if (ADAPT)
-      for (int k = tid; k < CAP / 32; k += T) L.dirty[k] = 0;
-    int mylive = 0;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int j = it * T + tid;
-      if (it * T < n && j < n) {
-        L.xs[j] = xr[it];
-        L.vs[j] = vr[it];
-        mylive += xr[it] > 0 ? 1 : 0;
-      }
+  for (int it = 0; it < IT; ++it) {
+    const int j = it * T + tid;
+    xr[it] = 0;
+    vr[it] = 0.0;
+    if (it * T < n && j < n) {
+      xr[it] = cur.xi[j];
+      vr[it] = cur.v[j];
     }
-    const int nlive = team_sum<W>(L, mylive, lane, wv);  // also orders the LDS stores
-    // prefetch the next cell while this one is processed
-    if (tn < n_tasks) fetch_cell<CAP, W>(nxt, tid, xr, vr);
-    const int tnn = tn + G;
-    CellTask nn{};
-    if (tnn < n_tasks) nn = tasks[tnn];
-
-    if (active) {
-      int ncoll = 0;
-      int nsub = 1;
-      if (!ADAPT) {
-        if (nlive >= 2) {
-          team_sort<CAP, W>(L, n, nlive, tid, lane, wv, c, s, 0u, dp->seed_lo, dp->seed_hi);
-          team_pairs<CAP, W, kPassPlain>(L, dp, n, nlive, tid, c, s, 0u, dp->q, false, o0,
-                                         &ncoll);
-        } else {
-          sink_clear_cell(dp, c, n, tid, T);
-        }
-      } else {
-        // Per-cell substepping: the substep length keeps every p <= 1 (p is
-        // clamped to 1), so gamma <= 1.  After max_substeps substeps the rest
-        // of the step is done in one unclamped substep and SUBSTEP_CAP is set.
-        const double dv = dp->dv;
-        double dt_left = dp->dt;
-        uint32_t u = 0;
-        const uint32_t umax = (uint32_t)dp->max_substeps;
-        while (dt_left > 0.0) {
-          const bool capped = u >= umax;
-          if (capped && tid == 0) atomicOr(dp->status, kFlagSubstepCap);
-          const int nl = u == 0 ? nlive : team_count_live<CAP, W>(L, n, tid, lane, wv);
-          if (nl < 2) {
-            if (capped) {
-              sink_clear_cell(dp, c, n, tid, T);
-              u += 1;
-            }
-            break;
-          }
-          team_sort<CAP, W>(L, n, nl, tid, lane, wv, c, s, u, dp->seed_lo, dp->seed_hi);
-          double pmax = team_pairs<CAP, W, kPassPmax>(L, dp, n, nl, tid, c, s, u, dt_left / dv,
-                                                      false, o0, &ncoll);
-          pmax = team_max<W>(L, pmax, lane, wv);
-          const double dt_sub = (capped || pmax <= 1.0) ? dt_left : dt_left / pmax;
-          team_pairs<CAP, W, kPassAdapt>(L, dp, n, nl, tid, c, s, u, dt_sub / dv, !capped, o0,
-                                         &ncoll);
-          // the next substep's attribute loads come from this same workgroup:
-          // one CU, one vector L1, so ordering the stores first is all it takes
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-          team_sync<W>();
-          dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
-          u += 1;
-          if (capped) break;
-        }
-        if (u == 0) sink_clear_cell(dp, c, n, tid, T);
-        nsub = (int)u;
-        team_sync<W>();
-        // write back the slots that changed
-        for (int j = tid; j < n; j += T) {
-          if ((L.dirty[j >> 5] >> (j & 31)) & 1u) {
-            cur.xi[j] = L.xs[j];
-            cur.v[j] = L.vs[j];
-          }
-        }
-      }
-      ncoll = team_sum<W>(L, ncoll, lane, wv);
-      if (tid == 0) add_stats(dp->stats, (unsigned long long)nlive, (unsigned long long)ncoll,
-                              (unsigned long long)nsub);
-    }
-    if (tn >= n_tasks) break;
-    cur = nxt;
-    nxt = nn;
-    tn = tnn;
-    team_sync<W>();  // the LDS of this cell is rewritten next
   }
+  const int c = cur.cell;
+  const SimDesc* dp = descs + cur.sim;
+  const int64_t o0 = cur.xi - dp->xi;
+  const uint32_t s = k_abs + dp->step_delta;
+  if (s >= dp->step_limit) return;  // uniform over the block
+  if (ADAPT)
+    for (int k = tid; k < CAP / 32; k += T) L.dirty[k] = 0;
+  int mylive = 0;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int j = it * T + tid;
+    if (it * T < n && j < n) {
+      L.xs[j] = xr[it];
+      L.vs[j] = vr[it];
+      mylive += xr[it] > 0 ? 1 : 0;
+    }
+  }
+  const int nlive = team_sum<W>(L, mylive, lane, wv);  // also orders the LDS stores
+
+  int ncoll = 0;
+  int nsub = 1;
+  if (!ADAPT) {
+    if (nlive >= 2) {
+      team_sort<CAP, W>(L, n, nlive, tid, lane, wv, c, s, 0u, dp->seed_lo, dp->seed_hi);
+      team_pairs<CAP, W, kPassPlain>(L, dp, n, nlive, tid, c, s, 0u, dp->q, false, o0, &ncoll);
+    } else {
+      sink_clear_cell(dp, c, n, tid, T);
+    }
+  } else {
+    // Per-cell substepping: the substep length keeps every p <= 1 (p is
+    // clamped to 1), so gamma <= 1.  After max_substeps substeps the rest of
+    // the step is done in one unclamped substep and SUBSTEP_CAP is raised.
+    const double dv = dp->dv;
+    double dt_left = dp->dt;
+    uint32_t u = 0;
+    const uint32_t umax = (uint32_t)dp->max_substeps;
+    while (dt_left > 0.0) {
+      const bool capped = u >= umax;
+      if (capped && tid == 0) atomicOr(dp->status, kFlagSubstepCap);
+      const int nl = u == 0 ? nlive : team_count_live<CAP, W>(L, n, tid, lane, wv);
+      if (nl < 2) {
+        if (capped) {
+          sink_clear_cell(dp, c, n, tid, T);
+          u += 1;
+        }
+        break;
+      }
+      team_sort<CAP, W>(L, n, nl, tid, lane, wv, c, s, u, dp->seed_lo, dp->seed_hi);
+      double pmax = team_pairs<CAP, W, kPassPmax>(L, dp, n, nl, tid, c, s, u, dt_left / dv,
+                                                  false, o0, &ncoll);
+      pmax = team_max<W>(L, pmax, lane, wv);
+      const double dt_sub = (capped || pmax <= 1.0) ? dt_left : dt_left / pmax;
+      team_pairs<CAP, W, kPassAdapt>(L, dp, n, nl, tid, c, s, u, dt_sub / dv, !capped, o0,
+                                     &ncoll);
+      // the next substep's attribute loads come from this same workgroup: one
+      // CU, one vector L1, so ordering the stores before them is all it takes
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      team_sync<W>();
+      dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
+      u += 1;
+      if (capped) break;
+    }
+    if (u == 0) sink_clear_cell(dp, c, n, tid, T);
+    nsub = (int)u;
+    team_sync<W>();
+    // write back the slots that changed
+    for (int j = tid; j < n; j += T) {
+      if ((L.dirty[j >> 5] >> (j & 31)) & 1u) {
+        cur.xi[j] = L.xs[j];
+        cur.v[j] = L.vs[j];
+      }
+    }
+  }
+  ncoll = team_sum<W>(L, ncoll, lane, wv);
+  if (tid == 0) add_stats(dp->stats, (unsigned long long)nlive, (unsigned long long)ncoll,
+                          (unsigned long long)nsub);
 }
 
 // ---------------------------------------------------------------------------
-// Big cells (> 512 slots): global bucket sort by the top key bits.
+// Mid-size cells (512 < n <= CAP, CAP up to 16384 slots): one workgroup of W
+// waves per cell.  Only the sort scratch lives in LDS (8 B per slot); xi and
+// v stay in global memory, where the pair gathers hit the caches that the
+// sort pass has just filled, and updates are written in place.  Adaptive
+// substeps re-read the cell after a workgroup-scope fence.
+// ---------------------------------------------------------------------------
+template <int CAP>
+struct alignas(16) MidLds {
+  uint32_t tmp[CAP];      // bucketed (key << nbits | slot), then uint16 permutation
+  uint32_t cnt[CAP + 4];  // bucket counters / starts, then double pre-products
+  int red_i[16];
+  double red_d[16];
+};
+
+constexpr int mid_waves(int cap) { return cap / 256 < 16 ? cap / 256 : 16; }
+
+// keys, liveness (from global xi), count, scan, scatter, rank; returns the
+// number of live SDs (uniform); the permutation is valid when it is >= 2
+template <int CAP, int W>
+__device__ __forceinline__ int mid_sort(MidLds<CAP>& L, const int64_t* xi, int n, int tid,
+                                        int lane, int wv, int c, uint32_t s, uint32_t u,
+                                        uint32_t k0, uint32_t k1) {
+  constexpr int T = 64 * W;
+  constexpr int I4 = CAP / (4 * T) > 0 ? CAP / (4 * T) : 1;
+  const int nbits = 32 - __clz(n - 1);
+  const int nb = 1 << nbits;
+  const int sh = 32 - nbits;
+  for (int i = 4 * tid; i < nb + 4; i += 4 * T)  // counters 0..nb, 16 bytes at a time
+    *reinterpret_cast<uint4*>(&L.cnt[i]) = make_uint4(0u, 0u, 0u, 0u);
+  __syncthreads();
+  uint32_t kr[I4][4], pos[I4][4];
+  uint32_t live[I4];
+  int mylive = 0;
+#pragma unroll
+  for (int i = 0; i < I4; ++i) {
+    const int g = T * i + tid;
+    live[i] = 0;
+    if (4 * g < n) {
+      long long xv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xv[e] = (4 * g + e < n) ? xi[4 * g + e] : 0;
+      const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)c, s, 2u * u), k0, k1);
+      kr[i][0] = w.x;
+      kr[i][1] = w.y;
+      kr[i][2] = w.z;
+      kr[i][3] = w.w;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (xv[e] > 0) {
+          live[i] |= 1u << e;
+          pos[i][e] = atomicAdd(&L.cnt[kr[i][e] >> sh], 1u);
+          ++mylive;
+        }
+      }
+    }
+  }
+  const int nlive = team_sum_r<W>(L.red_i, mylive, lane, wv);  // also a barrier
+  if (nlive < 2) return nlive;
+  {  // exclusive scan of the nb counters over the workgroup
+    const int per = nb >= T ? nb / T : 1;
+    const int first = tid * per;
+    int local = scan_load(L.cnt, first, per, nb);
+    int run = wave_excl_scan(local, lane);
+    if (lane == 63) L.red_i[wv] = run + local;
+    __syncthreads();
+    for (int k = 0; k < wv; ++k) run += L.red_i[k];
+    __syncthreads();
+    scan_store(L.cnt, first, per, nb, run);
+    if (tid == 0) L.cnt[nb] = (uint32_t)nlive;
+  }
+  __syncthreads();
+  uint32_t st[I4][4], len[I4][4];
+  int maxlen = 0;
+#pragma unroll
+  for (int i = 0; i < I4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      len[i][e] = 0;
+      if ((live[i] >> e) & 1) {
+        const uint32_t b = kr[i][e] >> sh;
+        st[i][e] = L.cnt[b];
+        len[i][e] = L.cnt[b + 1] - st[i][e];
+        L.tmp[st[i][e] + pos[i][e]] = (kr[i][e] << nbits) | (uint32_t)(4 * (T * i + tid) + e);
+        maxlen = max(maxlen, (int)len[i][e]);
+      }
+    }
+  __syncthreads();
+  uint32_t rk[I4][4];
+#pragma unroll
+  for (int i = 0; i < I4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rk[i][e] = st[i][e];
+  for (int k = 0; k < maxlen; ++k) {
+#pragma unroll
+    for (int i = 0; i < I4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if ((uint32_t)k < len[i][e]) {
+          const uint32_t me = (kr[i][e] << nbits) | (uint32_t)(4 * (T * i + tid) + e);
+          rk[i][e] += (L.tmp[st[i][e] + k] < me) ? 1u : 0u;
+        }
+      }
+  }
+  __syncthreads();
+  uint16_t* perm = reinterpret_cast<uint16_t*>(L.tmp);
+#pragma unroll
+  for (int i = 0; i < I4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if ((live[i] >> e) & 1) perm[rk[i][e]] = (uint16_t)(4 * (T * i + tid) + e);
+  __syncthreads();
+  return nlive;
+}
+
+template <int CAP, int W, int MODE>
+__device__ __forceinline__ double mid_pairs(MidLds<CAP>& L, const SimDesc* dp, int64_t* xi,
+                                            double* v, int n, int nlive, int tid, int c,
+                                            uint32_t s, uint32_t u, double q, bool clamp,
+                                            int64_t o0, int* ncoll) {
+  constexpr int T = 64 * W;
+  constexpr int I4 = CAP / (4 * T) > 0 ? CAP / (4 * T) : 1;
+  const int P = nlive >> 1;
+  const double S = (double)((nlive & 1) ? nlive : nlive - 1);
+  double* pre = reinterpret_cast<double*>(L.cnt);
+  const uint16_t* perm = reinterpret_cast<const uint16_t*>(L.tmp);
+  double pmax = 0.0;
+  int64_t* sink = (MODE == kPassPmax) ? nullptr : dp->sink;
+  const int64_t sink_base = sink ? 2 * dp->pair_base[c] : 0;
+#pragma unroll
+  for (int i = 0; i < I4; ++i) {
+    const int h = T * i + tid;
+    if (2 * h >= P) continue;
+    const uint2 o4 = *reinterpret_cast<const uint2*>(&perm[4 * h]);
+    const int aa[2] = {(int)(o4.x & 0xFFFFu), (int)(o4.y & 0xFFFFu)};
+    const int bs[2] = {(int)(o4.x >> 16), (int)(o4.y >> 16)};
+    uint4 w = make_uint4(0, 0, 0, 0);
+    if (MODE != kPassPmax) w = philox(make_uint4((uint32_t)h, (uint32_t)c, s, 2u * u + 1u),
+                                      dp->seed_lo, dp->seed_hi);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int m = 2 * h + e;
+      if (m >= P) break;
+      const int a = aa[e], bb = bs[e];
+      const long long xa = xi[a], xb = xi[bb];
+      const double va = v[a], vb = v[bb];
+      double p;
+      if (MODE == kPassAdapt) {
+        p = pre[m] * q;
+      } else {
+        const double kv = coal_kernel(dp->kernel, dp->b, va, vb);
+        const double pp = ((double)(xa > xb ? xa : xb) * kv) * S;
+        if (MODE == kPassPmax) {
+          pre[m] = pp;
+          pmax = fmax(pmax, pp * q);
+          continue;
+        }
+        p = pp * q;
+      }
+      if (clamp && p > 1.0) p = 1.0;
+      const double phi = e == 0 ? uniform53(w.x, w.y) : uniform53(w.z, w.w);
+      const long long gamma = collisions(p, phi, dp->status);
+      if (sink) {
+        sink[sink_base + 2 * m] = (int64_t)((uint64_t)a | ((uint64_t)bb << 32));
+        sink[sink_base + 2 * m + 1] = gamma;
+      }
+      if (gamma > 0) {
+        *ncoll += 1;
+        update_pair(xi, v, a, bb, xa, xb, va, vb, gamma, dp->attrs, dp->n_slots, dp->n_attr,
+                    o0 + a, o0 + bb);
+      }
+    }
+  }
+  if (sink && MODE != kPassPmax) {
+    for (int m = P + tid; m < (n >> 1); m += T) {
+      sink[sink_base + 2 * m] = -1;
+      sink[sink_base + 2 * m + 1] = -1;
+    }
+  }
+  __syncthreads();
+  return pmax;
+}
+
+template <int CAP, int W, bool ADAPT>
+__global__ void __launch_bounds__(64 * W) k_cells_mid(const SimDesc* __restrict__ descs,
+                                                      const CellTask* __restrict__ tasks,
+                                                      uint32_t k_abs) {
+  constexpr int T = 64 * W;
+  extern __shared__ __align__(16) unsigned char smem[];
+  MidLds<CAP>& L = *reinterpret_cast<MidLds<CAP>*>(smem);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const CellTask ct = tasks[blockIdx.x];
+  const SimDesc* dp = descs + ct.sim;
+  const uint32_t s = k_abs + dp->step_delta;
+  if (s >= dp->step_limit) return;  // uniform over the block
+  const int n = ct.n;
+  const int c = ct.cell;
+  int64_t* xi = ct.xi;
+  double* v = ct.v;
+  const int64_t o0 = xi - dp->xi;
+  int ncoll = 0;
+  int nsub = 1;
+  int nlive0 = 0;
+  if (!ADAPT) {
+    const int nl = mid_sort<CAP, W>(L, xi, n, tid, lane, wv, c, s, 0u, dp->seed_lo, dp->seed_hi);
+    nlive0 = nl;
+    if (nl >= 2)
+      mid_pairs<CAP, W, kPassPlain>(L, dp, xi, v, n, nl, tid, c, s, 0u, dp->q, false, o0,
+                                    &ncoll);
+    else
+      sink_clear_cell(dp, c, n, tid, T);
+  } else {
+    const double dv = dp->dv;
+    double dt_left = dp->dt;
+    uint32_t u = 0;
+    const uint32_t umax = (uint32_t)dp->max_substeps;
+    while (dt_left > 0.0) {
+      const bool capped = u >= umax;
+      if (capped && tid == 0) atomicOr(dp->status, kFlagSubstepCap);
+      const int nl = mid_sort<CAP, W>(L, xi, n, tid, lane, wv, c, s, u, dp->seed_lo,
+                                      dp->seed_hi);
+      if (u == 0) nlive0 = nl;
+      if (nl < 2) {
+        if (capped) {
+          sink_clear_cell(dp, c, n, tid, T);
+          u += 1;
+        }
+        break;
+      }
+      double pmax = mid_pairs<CAP, W, kPassPmax>(L, dp, xi, v, n, nl, tid, c, s, u,
+                                                 dt_left / dv, false, o0, &ncoll);
+      pmax = team_max_r<W>(L.red_d, pmax, lane, wv);
+      const double dt_sub = (capped || pmax <= 1.0) ? dt_left : dt_left / pmax;
+      mid_pairs<CAP, W, kPassAdapt>(L, dp, xi, v, n, nl, tid, c, s, u, dt_sub / dv, !capped, o0,
+                                    &ncoll);
+      // updates of this substep are read by other threads of this workgroup next
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __syncthreads();
+      dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
+      u += 1;
+      if (capped) break;
+    }
+    if (u == 0) sink_clear_cell(dp, c, n, tid, T);
+    nsub = (int)u;
+  }
+  ncoll = team_sum_r<W>(L.red_i, ncoll, lane, wv);
+  if (tid == 0) add_stats(dp->stats, (unsigned long long)nlive0, (unsigned long long)ncoll,
+                          (unsigned long long)nsub);
+}
+
+// ---------------------------------------------------------------------------
+// Big cells (above the mid-size limit): global bucket sort by the top key bits.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t bucket_of(uint32_t key, int bbits) {
   return bbits ? (key >> (32 - bbits)) : 0u;
@@ -934,40 +1204,37 @@ void set_lds_limits() {
   static bool done = false;
   if (done) return;
   done = true;
+  const int lim = 160 * 1024;
   (void)hipFuncSetAttribute((const void*)k_big_rank, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
+                            lim);
+  (void)hipFuncSetAttribute((const void*)k_cells_mid<2048, mid_waves(2048), false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_cells_mid<2048, mid_waves(2048), true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_cells_mid<4096, mid_waves(4096), false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_cells_mid<4096, mid_waves(4096), true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_cells_mid<8192, mid_waves(8192), false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_cells_mid<8192, mid_waves(8192), true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_cells_mid<16384, mid_waves(16384), false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_cells_mid<16384, mid_waves(16384), true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipGetLastError();
-}
-
-// resident workgroups of one cell kernel on this device (cached per instantiation)
-template <int CAP, int W, bool ADAPT>
-static int persistent_grid() {
-  static int grid = 0;
-  if (grid == 0) {
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cells<CAP, W, ADAPT>, 64 * W, 0) !=
-            hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus < 1)
-      cus = 1;
-    (void)hipGetLastError();
-    grid = per_cu * cus;
-  }
-  return grid;
 }
 
 template <int CAP, int W>
 static void launch_class_w(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st) {
   const int np = p.n_plain[cls], na = p.n_wave[cls] - p.n_plain[cls];
   if (np > 0)
-    hipLaunchKernelGGL((k_cells<CAP, W, false>), dim3(std::min(np, persistent_grid<CAP, W, false>())),
-                       dim3(64 * W), 0, st, p.desc, p.wave_tasks[cls], np, k_abs);
+    hipLaunchKernelGGL((k_cells<CAP, W, false>), dim3(np), dim3(64 * W), 0, st, p.desc,
+                       p.wave_tasks[cls], k_abs);
   if (na > 0)
-    hipLaunchKernelGGL((k_cells<CAP, W, true>), dim3(std::min(na, persistent_grid<CAP, W, true>())),
-                       dim3(64 * W), 0, st, p.desc, p.wave_tasks[cls] + np, na, k_abs);
+    hipLaunchKernelGGL((k_cells<CAP, W, true>), dim3(na), dim3(64 * W), 0, st, p.desc,
+                       p.wave_tasks[cls] + np, k_abs);
 }
 
 template <int CAP>
@@ -980,11 +1247,37 @@ static void launch_class(const PlanDev& p, int cls, uint32_t k_abs, int w, hipSt
   }
 }
 
+size_t mid_lds_bytes(int cls) {
+  switch (cls) {
+    case 0: return sizeof(MidLds<2048>);
+    case 1: return sizeof(MidLds<4096>);
+    case 2: return sizeof(MidLds<8192>);
+    default: return sizeof(MidLds<16384>);
+  }
+}
+
+template <int CAP>
+static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st) {
+  constexpr int W = mid_waves(CAP);
+  const int np = p.n_mid_plain[cls], na = p.n_mid[cls] - p.n_mid_plain[cls];
+  const unsigned lds = (unsigned)sizeof(MidLds<CAP>);
+  if (np > 0)
+    hipLaunchKernelGGL((k_cells_mid<CAP, W, false>), dim3(np), dim3(64 * W), lds, st, p.desc,
+                       p.mid_tasks[cls], k_abs);
+  if (na > 0)
+    hipLaunchKernelGGL((k_cells_mid<CAP, W, true>), dim3(na), dim3(64 * W), lds, st, p.desc,
+                       p.mid_tasks[cls] + np, k_abs);
+}
+
 hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st) {
   launch_class<512>(p, 3, k_abs, waves_per_cell, st);
   launch_class<256>(p, 2, k_abs, waves_per_cell, st);
   launch_class<128>(p, 1, k_abs, waves_per_cell, st);
   launch_class<64>(p, 0, k_abs, waves_per_cell, st);
+  launch_mid<16384>(p, 3, k_abs, st);
+  launch_mid<8192>(p, 2, k_abs, st);
+  launch_mid<4096>(p, 1, k_abs, st);
+  launch_mid<2048>(p, 0, k_abs, st);
   if (p.n_big > 0) {
     hipLaunchKernelGGL(k_big_count, dim3(p.n_chunks), dim3(256), 0, st, p.desc, p.big, p.chunks,
                        p.bucket_cnt, p.task_live, k_abs);

@@ -117,7 +117,9 @@ def test_golovin_tunings_same_result(B, orc):
     st = I.random_cells(64, 900, n_attr=1, rng_seed=9, p_boost=100.0)
     for tu in [dict(wave_class_mask=8, waves_per_cell=1, big_bucket_target=32),
                dict(wave_class_mask=15, waves_per_cell=8, big_bucket_target=1024),
-               dict(wave_class_mask=10, waves_per_cell=2, big_bucket_target=128)]:
+               dict(wave_class_mask=10, waves_per_cell=2, big_bucket_target=128),
+               dict(wave_class_mask=12, waves_per_cell=4, big_bucket_target=64, mid_max_slots=0),
+               dict(wave_class_mask=8, waves_per_cell=2, mid_max_slots=2048)]:
         say(f"tuning {tu}")
         assert _compare_run(B, orc, st, 6, tuning=tu, label=str(tu))
 
@@ -211,6 +213,14 @@ def test_adaptive_golovin_bit_exact(B, orc):
     st.adaptive = True
     say("adaptive golovin random cells")
     assert _compare_run(B, orc, st, 8, label="adaptive-golovin")
+
+
+def test_adaptive_mid_cells_bit_exact(B, orc):
+    """Adaptive substeps in the mid-size kernel (cells of 513..16384 slots)."""
+    st = I.random_cells(12, 3000, n_attr=2, rng_seed=33, p_boost=1e3)
+    st.adaptive = True
+    say("adaptive golovin mid-size cells")
+    assert _compare_run(B, orc, st, 6, label="adaptive-mid")
 
 
 def test_adaptive_geometric_drizzle(B, orc):
@@ -378,7 +388,7 @@ def test_invalid_inputs(B):
     bad.cell_off[2] = bad.cell_off[3] + 1
     with pytest.raises(B.SdmError):
         B.Sim(bad)
-    big = I.golovin_box(1024)
+    big = I.golovin_box(20000)  # adaptive mode takes cells of up to 16384 slots
     big.adaptive = True
     with pytest.raises(B.SdmError):
         B.Sim(big)
