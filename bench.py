@@ -66,8 +66,8 @@ def traffic_from_profiles(kernel_name, workload, launches_bytes):
         return None
     if d.get("kernel_source_sha") != kernel_source_sha():
         return None
-    scale = d.get("copy_scale", 1.0)
-    return (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0 * scale
+    # per-dispatch KiB, already scaled by the copy probe (see the json's commands)
+    return (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0
 
 
 def cpu_baseline(state, n_cells_sample, steps):
