@@ -411,3 +411,85 @@ def test_empty_and_tiny(B, orc):
     g.step(3)
     assert B.sdm_get_step(g.handle) == 3
     g.close()
+
+
+def test_autotune_keeps_results_and_caches(B, orc, tmp_path):
+    """The autotuner times shapes on a scratch copy: the handle's state and
+    counter are untouched, results after tuning still match the oracle, and
+    a second handle with the same key reuses the cached choice."""
+    st = I.random_cells(64, 900, n_attr=1, rng_seed=91, p_boost=30.0)
+    g = GpuRun(B, st)
+    scratch = B.workspace_tensor(B.sdm_autotune_scratch_bytes(g.sim.handle))
+    cache = str(tmp_path / "tune.jsonl")
+    say("autotune random cells")
+    t1 = B.sdm_autotune(g.sim.handle, scratch, trial_steps=2, cache_path=cache).as_dict()
+    say(f"  chosen {t1}")
+    xi, v, _ = g.state()
+    assert np.array_equal(xi, st.xi) and np.array_equal(v, st.v)
+    assert B.sdm_get_step(g.sim.handle) == 0
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"key"' in lines[0]
+    o = st.copy()
+    cfg = ocfg(orc, o)
+    for s in range(4):
+        g.step(1)
+        orc.step(cfg, o.xi, o.v, o.attrs, o.cell_off, s)
+    xi, v, at = g.state()
+    assert np.array_equal(xi, o.xi) and np.array_equal(v, o.v) and np.array_equal(at, o.attrs)
+    g.close()
+    g2 = GpuRun(B, st)
+    t2 = B.sdm_autotune(g2.sim.handle, None, trial_steps=2, cache_path=cache).as_dict()
+    assert t2 == t1
+    assert len(open(cache).read().strip().splitlines()) == 1
+    g2.close()
+
+
+def _sub_state(st, cells):
+    """Only the given cells keep their slots (cell indices unchanged)."""
+    counts = np.diff(st.cell_off)
+    keep = np.zeros(st.n_cells, dtype=bool)
+    keep[cells] = True
+    off = np.zeros(st.n_cells + 1, dtype=np.int64)
+    np.cumsum(np.where(keep, counts, 0), out=off[1:])
+    idx = np.concatenate([np.arange(st.cell_off[c], st.cell_off[c + 1]) for c in sorted(cells)])
+    return idx, off
+
+
+def test_full_grid256_sampled_parity(B, orc):
+    """The benchmark's workload at full size (256 x 256 cells, 16.8 M SDs,
+    adaptive geometric, 6 attributes) in the benchmark's launch shape: one GPU
+    step, then the oracle recomputes a sample of cells one by one."""
+    st = I.grid_256x256()
+    say(f"full 256x256 grid: {st.n_slots} slots")
+    g = GpuRun(B, st, tuning=dict(wave_class_mask=8, waves_per_cell=1))
+    g.step(1)
+    xi, v, at = g.state()
+    rng = np.random.default_rng(5)
+    counts = np.diff(st.cell_off)
+    cells = set(rng.choice(st.n_cells, size=600, replace=False).tolist())
+    cells |= {int(np.argmax(counts)), int(np.argmin(counts)), 0, st.n_cells - 1}
+    cells = sorted(cells)
+    idx, off = _sub_state(st, cells)
+    o_xi = st.xi[idx].copy()
+    o_v = st.v[idx].copy()
+    o_a = np.ascontiguousarray(st.attrs[:, idx])
+    cfg = orc.OracleConfig(n_slots=len(idx), n_cells=st.n_cells, n_attr=st.n_attr, dt=st.dt,
+                           dv=st.dv, b=st.b, kernel=st.kernel, adaptive=True, seed=st.seed)
+    out = orc.step(cfg, o_xi, o_v, o_a, off, 0, want_substeps=True)
+    bad = 0
+    for c in cells:
+        gs = slice(st.cell_off[c], st.cell_off[c + 1])
+        os_ = slice(off[c], off[c + 1])
+        same = (np.array_equal(xi[gs], o_xi[os_]) and rel_close(v[gs], o_v[os_], 1e-12)
+                and rel_close(at[:, gs], o_a[:, os_], 1e-12))
+        bad += 0 if same else 1
+    say(f"  sampled {len(cells)} cells, {int((out['substeps'][cells] > 1).sum())} with substeps, "
+        f"mismatching cells {bad}")
+    assert bad <= 1  # a last-bit cube-root difference may flip one gamma (geometric kernel)
+    g.close()
+
+
+def test_full_grid64_teacher_forced(B, orc):
+    """The 64 x 64 grid at full size (min(Poisson(128), 200) SDs, 3 attributes)."""
+    st = I.grid_64x64()
+    _teacher_forced(B, orc, st, 5, "geometric 64x64 grid (full size)")
