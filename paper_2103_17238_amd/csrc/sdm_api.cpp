@@ -231,6 +231,15 @@ struct Plan {
   PlanDev dev{};
   std::vector<SimDesc> desc;  // host copy of the device descriptors
   uint32_t counter = 0;       // launch step of the next step
+  sdm::SideStream side;       // created at the first step
+  Plan() = default;
+  Plan(const Plan&) = delete;
+  Plan& operator=(const Plan&) = delete;
+  ~Plan() {
+    if (side.fork) (void)hipEventDestroy(side.fork);
+    if (side.join) (void)hipEventDestroy(side.join);
+    if (side.stream) (void)hipStreamDestroy(side.stream);
+  }
 };
 
 static SimDesc make_desc(const sdm_sim* s, uint32_t delta) {
@@ -371,9 +380,17 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
     const int64_t left = s->step < s->limit ? (int64_t)(s->limit - s->step) : 0;
     active = std::max<int64_t>(active, std::min<int64_t>(left, n_steps));
   }
+  if (active > 0 && !p->side.stream) {
+    if (hipStreamCreateWithFlags(&p->side.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->side.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->side.join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return SDM_EDEVICE;
+    }
+  }
   for (int64_t k = 0; k < active; ++k) {
-    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->tuning.waves_per_cell, st) !=
-        hipSuccess)
+    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->tuning.waves_per_cell, st,
+                         p->side) != hipSuccess)
       return SDM_EDEVICE;
   }
   p->counter += (uint32_t)n_steps;

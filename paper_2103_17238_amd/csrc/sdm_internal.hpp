@@ -112,8 +112,15 @@ struct PlanDev {
   uint32_t* ord;
 };
 
+// second stream (and fork/join events) for concurrent class launches
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 // launches (sdm_kernels.hip)
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st);
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st,
+                       const SideStream& side);
 hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
                           double* attr_sums, const double* edges, int n_bins, double* spectrum,
                           hipStream_t st);

@@ -1269,11 +1269,26 @@ static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st
                        p.mid_tasks[cls] + np, k_abs);
 }
 
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st) {
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st,
+                       const SideStream& side) {
+  // cells of up to 256 slots run beside the 512-slot class on a second
+  // stream: the launches fill each other's tails
+  const bool fork = side.stream && p.n_wave[3] > 0 &&
+                    (p.n_wave[0] > 0 || p.n_wave[1] > 0 || p.n_wave[2] > 0);
+  hipStream_t st2 = st;
+  if (fork) {
+    if (hipEventRecord(side.fork, st) != hipSuccess ||
+        hipStreamWaitEvent(side.stream, side.fork, 0) != hipSuccess)
+      return hipErrorUnknown;
+    st2 = side.stream;
+  }
+  launch_class<256>(p, 2, k_abs, waves_per_cell, st2);
+  launch_class<128>(p, 1, k_abs, waves_per_cell, st2);
+  launch_class<64>(p, 0, k_abs, waves_per_cell, st2);
   launch_class<512>(p, 3, k_abs, waves_per_cell, st);
-  launch_class<256>(p, 2, k_abs, waves_per_cell, st);
-  launch_class<128>(p, 1, k_abs, waves_per_cell, st);
-  launch_class<64>(p, 0, k_abs, waves_per_cell, st);
+  if (fork && (hipEventRecord(side.join, st2) != hipSuccess ||
+               hipStreamWaitEvent(st, side.join, 0) != hipSuccess))
+    return hipErrorUnknown;
   launch_mid<16384>(p, 3, k_abs, st);
   launch_mid<8192>(p, 2, k_abs, st);
   launch_mid<4096>(p, 1, k_abs, st);

@@ -215,6 +215,23 @@ def test_adaptive_golovin_bit_exact(B, orc):
     assert _compare_run(B, orc, st, 8, label="adaptive-golovin")
 
 
+@pytest.mark.parametrize("boost,uniform", [(300.0, False), (3e4, False), (0.0, True)])
+def test_adaptive_attributes_many_collisions(B, orc, boost, uniform):
+    """Attributes under adaptive substepping, bit-exact: cells of up to 500
+    SDs with 3 attributes, from a few collisions per step to every pair of a
+    cell colliding (and splitting) in each of many substeps."""
+    st = I.random_cells(24, 500, n_attr=3, rng_seed=37, p_boost=max(boost, 1.0))
+    if uniform:
+        live = st.xi > 0
+        st.xi[live] = 1000
+        st.v[:] = float(np.mean(st.v))
+        # every pair gets the same p: 5 in a 50-SD cell, 50 in a 500-SD cell
+        st.b = 5.0 * st.dv / (1000 * 2 * st.v[0] * 49 * st.dt)
+    st.adaptive = True
+    say(f"adaptive attributes boost={boost} uniform={uniform}")
+    assert _compare_run(B, orc, st, 4, label=f"adaptive-attrs-{boost}-{uniform}")
+
+
 def test_adaptive_mid_cells_bit_exact(B, orc):
     """Adaptive substeps in the mid-size kernel (cells of 513..16384 slots)."""
     st = I.random_cells(12, 3000, n_attr=2, rng_seed=33, p_boost=1e3)
