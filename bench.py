@@ -54,6 +54,21 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+CLASS_CAPS = (64, 128, 256, 384, 512)
+
+
+def launched_classes(state, mask):
+    """Capacities of the workgroup-per-cell classes that get cells."""
+    import numpy as np
+
+    mask |= 0x10
+    caps = [c for k, c in enumerate(CLASS_CAPS) if (mask >> k) & 1]
+    n = np.diff(state.cell_off)
+    n = n[(n > 0) & (n <= 512)]
+    used = sorted({caps[int(np.searchsorted(caps, x))] for x in np.unique(n)})
+    return used
+
+
 def traffic_from_profiles(kernel_name, workload, launches_bytes):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
     were taken on the current kernel source; else None."""
@@ -155,8 +170,8 @@ def main():
         # cells of <= 256 slots in their own class on a second stream (two
         # concurrent launches); waves per cell
         best = None
-        for mask in (8, 12):
-            for wpb in (1, 2, 4):
+        for mask in (0x10, 0x14, 0x18, 0x1C):
+            for wpb in (1, 2):
                 t = B.sdm_get_tuning(sim.handle)
                 t.wave_class_mask, t.waves_per_cell = mask, wpb
                 # time on a scratch copy so the measured state is untouched
@@ -206,14 +221,12 @@ def main():
     value = live / (total_ms / 1e3)
     cell_grid = args.workload in ("grid256", "grid64")
     mode = "adaptive" if state.adaptive else "plain"
-    two = tuning["wave_class_mask"] == 12
+    caps = launched_classes(state, tuning["wave_class_mask"])
+    two = len(caps) > 1
     if not cell_grid:
         kernel_name = "whole_step"
-    elif two:  # both launches of the step, concurrent on two streams
-        kernel_name = (f"k_cells<256,{tuning['waves_per_cell']},{mode}> || "
-                       f"k_cells<512,{tuning['waves_per_cell']},{mode}>")
-    else:
-        kernel_name = f"k_cells<512,{tuning['waves_per_cell']},{mode}>"
+    else:  # the step's cell launches (concurrent when there are several)
+        kernel_name = " || ".join(f"k_cells<{c},{tuning['waves_per_cell']},{mode}>" for c in caps)
     achieved = alg_bytes / K / (per_launch_ms.mean() / 1e3) / 1e9
     traffic = traffic_from_profiles("k_cells", args.workload, alg_bytes / K)
     line = {
@@ -236,7 +249,7 @@ def main():
             "n_attr": A,
             "kernel": "geometric" if state.kernel == 1 else "golovin",
             "adaptive": bool(state.adaptive),
-            "parallelism": ("1 GPU, two concurrent cell launches per step (two streams)" if two
+            "parallelism": ("1 GPU, concurrent cell launches per step (two streams)" if two
                             else "1 GPU, one fused launch per step") if cell_grid else "1 GPU",
             "tuning": tuning,
             "tuning_source": tuning_note,

@@ -91,9 +91,10 @@ typedef struct {
 
 /* Launch-shape knobs.  They change speed only, never results. */
 typedef struct {
-  int32_t wave_class_mask;   /* bit k (k = 0..3): cells of <= 64 << k slots get their own
-                                workgroup-per-cell launch; cells go to the smallest enabled
-                                class that fits; bit 3 (512) is always on */
+  int32_t wave_class_mask;   /* bit k (k = 0..4) enables the workgroup-per-cell class of
+                                64, 128, 256, 384, 512 slots; a cell goes to the smallest
+                                enabled class that fits; bit 4 (512) is always on.  Classes
+                                up to 256 slots run on a second stream beside the larger ones */
   int32_t waves_per_cell;    /* 1, 2, 4 or 8: wavefronts in the workgroup of one cell */
   int32_t big_bucket_target; /* cells on the big-cell path: expected SDs per sort bucket,
                                 32..1024 */

@@ -40,7 +40,7 @@ inline int ceil_log2(int64_t x) {
 
 sdm_tuning default_tuning() {
   sdm_tuning t;
-  t.wave_class_mask = 0xF;
+  t.wave_class_mask = sdm::kClassAll;
   t.waves_per_cell = 1;
   t.big_bucket_target = 256;
   t.lpt_order = 1;
@@ -51,7 +51,7 @@ sdm_tuning default_tuning() {
 bool tuning_ok(const sdm_tuning& t) {
   const int w = t.waves_per_cell;
   return (w == 1 || w == 2 || w == 4 || w == 8) && t.big_bucket_target >= sdm::kMinBucketTarget &&
-         t.big_bucket_target <= 1024 && (t.wave_class_mask & ~0xF) == 0 &&
+         t.big_bucket_target <= 1024 && (t.wave_class_mask & ~sdm::kClassAll) == 0 &&
          t.mid_max_slots >= 0 && t.mid_max_slots <= sdm::kMidCapMax;
 }
 
@@ -84,7 +84,7 @@ struct sdm_sim {
 // ---------------------------------------------------------------------------
 struct Tables {
   std::vector<sdm::CellTask> wave[sdm::kNumClasses];  // plain-mode cells first, then adaptive
-  int n_plain[sdm::kNumClasses] = {0, 0, 0, 0};
+  int n_plain[sdm::kNumClasses] = {};
   std::vector<sdm::CellTask> mid[sdm::kNumMid];  // plain-mode cells first, then adaptive
   int n_mid_plain[sdm::kNumMid] = {0, 0, 0, 0};
   bool adaptive_big = false;  // an adaptive-mode cell fell to the big-cell path
@@ -108,7 +108,7 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
   };
   std::vector<Item> items[sdm::kNumClasses];
   std::vector<Item> mids[sdm::kNumMid];
-  const int mask = tu.wave_class_mask | 0x8;
+  const int mask = tu.wave_class_mask | sdm::kClassTop;
   for (int i = 0; i < (int)ms.size(); ++i) {
     const auto& off = ms[i]->off;
     const int C = ms[i]->cfg.n_cells;
@@ -653,7 +653,7 @@ sdm_status sdm_get_tuning(const sdm_sim* s, sdm_tuning* t) {
 sdm_status sdm_set_tuning(sdm_sim* s, const sdm_tuning* t, void* stream) {
   if (!s || !t || !tuning_ok(*t)) return SDM_EINVAL;
   s->tuning = *t;
-  s->tuning.wave_class_mask |= 0x8;
+  s->tuning.wave_class_mask |= sdm::kClassTop;
   s->plan->tuning = s->tuning;
   s->plan->counter = s->step;
   return plan_setup(s->plan, reinterpret_cast<hipStream_t>(stream));
@@ -853,17 +853,23 @@ extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_byt
   };
 
   // candidate shapes
-  bool has_small[4] = {false, false, false, false}, has_big = false, has_mid = false;
+  bool has_small[sdm::kNumClasses] = {}, has_big = false, has_mid = false;
   for (int c = 0; c < s->cfg.n_cells; ++c) {
     const int64_t n = s->off[c + 1] - s->off[c];
-    if (n > sdm::kMidCapMax) has_big = true;
-    else if (n > sdm::kWaveCapMax) has_mid = true;
-    else if (n > 0) has_small[n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3] = true;
+    if (n > sdm::kMidCapMax) {
+      has_big = true;
+    } else if (n > sdm::kWaveCapMax) {
+      has_mid = true;
+    } else if (n > 0) {
+      int k = 0;
+      while (n > sdm::class_cap(k)) ++k;
+      has_small[k] = true;
+    }
   }
-  std::vector<int> masks = {0x8};
-  for (int m : {0xC, 0xE, 0xF, 0xA, 0x9}) {  // only masks that split populated classes
+  std::vector<int> masks = {sdm::kClassTop};
+  for (int m : {0x18, 0x14, 0x1C, 0x1E, 0x1F, 0x12, 0x11}) {  // masks that split populated classes
     bool useful = false;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < sdm::kNumClasses - 1; ++k)
       if (((m >> k) & 1) && has_small[k]) useful = true;
     if (useful) masks.push_back(m);
   }
@@ -875,9 +881,9 @@ extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_byt
     const bool bigs = has_big || (mm == 0 && has_mid);
     const std::vector<int> targets =
         bigs ? std::vector<int>{64, 128, 256, 512} : std::vector<int>{256};
-    const std::vector<int> waves = has_small[0] || has_small[1] || has_small[2] || has_small[3]
-                                       ? std::vector<int>{1, 2, 4, 8}
-                                       : std::vector<int>{1};
+    bool any_small = false;
+    for (bool h : has_small) any_small = any_small || h;
+    const std::vector<int> waves = any_small ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1};
     for (int m : masks)
       for (int wpb : waves)
         for (int tg : targets) cands.push_back({m, wpb, tg, 1, mm});

@@ -9,7 +9,7 @@ namespace sdm {
 
 constexpr int kStatSlots = 256;   // spread of the statistics counters (fewer atomics per address)
 constexpr int kStatFields = 4;    // live SD-steps, colliding pairs, cell substeps, cell steps
-constexpr int kNumClasses = 4;    // workgroup-per-cell capacities 64, 128, 256, 512 slots
+constexpr int kNumClasses = 5;    // workgroup-per-cell capacities 64, 128, 256, 384, 512 slots
 constexpr int kWaveCapMax = 512;  // cells above this go to the mid-size or big-cell path
 constexpr int kNumMid = 4;        // mid-size capacities 2048, 4096, 8192, 16384 slots
 constexpr int kMidCapMax = 16384;
@@ -22,7 +22,9 @@ constexpr uint32_t kFlagGammaCap = 2u;
 constexpr uint32_t kFlagBucketOverflow = 4u;
 constexpr uint32_t kFlagInvalid = 8u;
 
-inline int class_cap(int k) { return 64 << k; }
+inline int class_cap(int k) { return k < 3 ? 64 << k : (k == 3 ? 384 : 512); }
+constexpr int kClassAll = 0x1F;  // every class enabled
+constexpr int kClassTop = 0x10;  // the 512-slot class, always enabled
 inline int mid_cap(int k) { return 2048 << k; }
 
 // Per-simulation parameters read by every step kernel (device array, one per member).

@@ -226,12 +226,14 @@ __device__ __forceinline__ void scan_store(uint32_t* cnt, int first, int per, in
 // sort a thread owns 4 consecutive slots, i.e. exactly the 4 words of one
 // Philox call, so keys never go through LDS.
 // ---------------------------------------------------------------------------
+constexpr int pow2_ceil(int x) { return x <= 1 ? 1 : 2 * pow2_ceil((x + 1) / 2); }
+
 template <int CAP>
 struct alignas(16) CellLds {
   long long xs[CAP];  // multiplicities (slot order)
   double vs[CAP];     // volumes (slot order)
   uint32_t tmp[CAP];  // bucketed (key << nbits | slot), then uint16 permutation
-  uint32_t cnt[CAP + 4];     // bucket counters / starts, then double pre-products
+  uint32_t cnt[pow2_ceil(CAP) + 4];  // bucket counters / starts, then double pre-products
   uint32_t dirty[CAP / 32];  // adaptive mode: slots to write back
   int red_i[8];              // cross-wave reductions
   double red_d[8];
@@ -293,7 +295,7 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
                                           int wv, int c, uint32_t s, uint32_t u, uint32_t k0,
                                           uint32_t k1) {
   constexpr int T = 64 * W;
-  constexpr int I4 = CAP / (4 * T) > 0 ? CAP / (4 * T) : 1;  // 4-slot groups per thread
+  constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);  // 4-slot groups per thread
   const int nbits = 32 - __clz(n - 1);                        // n >= 2
   const int nb = 1 << nbits;
   const int sh = 32 - nbits;
@@ -396,7 +398,7 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
                                              int nlive, int tid, int c, uint32_t s, uint32_t u,
                                              double q, bool clamp, int64_t o0, int* ncoll) {
   constexpr int T = 64 * W;
-  constexpr int I4 = CAP / (4 * T) > 0 ? CAP / (4 * T) : 1;
+  constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);
   const int P = nlive >> 1;
   const double S = (double)((nlive & 1) ? nlive : nlive - 1);
   double* pre = reinterpret_cast<double*>(L.cnt);  // P <= CAP/2 doubles fit in cnt
@@ -494,7 +496,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
                                                   const CellTask* __restrict__ tasks,
                                                   uint32_t k_abs) {
   constexpr int T = 64 * W;
-  constexpr int IT = CAP / T > 0 ? CAP / T : 1;
+  constexpr int IT = (CAP + T - 1) / T;
   __shared__ CellLds<CAP> L;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -616,7 +618,7 @@ __device__ __forceinline__ int mid_sort(MidLds<CAP>& L, const int64_t* xi, int n
                                         int lane, int wv, int c, uint32_t s, uint32_t u,
                                         uint32_t k0, uint32_t k1) {
   constexpr int T = 64 * W;
-  constexpr int I4 = CAP / (4 * T) > 0 ? CAP / (4 * T) : 1;
+  constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);
   const int nbits = 32 - __clz(n - 1);
   const int nb = 1 << nbits;
   const int sh = 32 - nbits;
@@ -713,7 +715,7 @@ __device__ __forceinline__ double mid_pairs(MidLds<CAP>& L, const SimDesc* dp, i
                                             uint32_t s, uint32_t u, double q, bool clamp,
                                             int64_t o0, int* ncoll) {
   constexpr int T = 64 * W;
-  constexpr int I4 = CAP / (4 * T) > 0 ? CAP / (4 * T) : 1;
+  constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);
   const int P = nlive >> 1;
   const double S = (double)((nlive & 1) ? nlive : nlive - 1);
   double* pre = reinterpret_cast<double*>(L.cnt);
@@ -1196,6 +1198,7 @@ size_t cell_lds_bytes(int cls) {
     case 0: return sizeof(CellLds<64>);
     case 1: return sizeof(CellLds<128>);
     case 2: return sizeof(CellLds<256>);
+    case 3: return sizeof(CellLds<384>);
     default: return sizeof(CellLds<512>);
   }
 }
@@ -1271,9 +1274,9 @@ static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st
 
 hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st,
                        const SideStream& side) {
-  // cells of up to 256 slots run beside the 512-slot class on a second
-  // stream: the launches fill each other's tails
-  const bool fork = side.stream && p.n_wave[3] > 0 &&
+  // cells of up to 256 slots run beside the 384- and 512-slot classes on a
+  // second stream: the launches fill each other's tails
+  const bool fork = side.stream && (p.n_wave[3] > 0 || p.n_wave[4] > 0) &&
                     (p.n_wave[0] > 0 || p.n_wave[1] > 0 || p.n_wave[2] > 0);
   hipStream_t st2 = st;
   if (fork) {
@@ -1285,7 +1288,8 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hip
   launch_class<256>(p, 2, k_abs, waves_per_cell, st2);
   launch_class<128>(p, 1, k_abs, waves_per_cell, st2);
   launch_class<64>(p, 0, k_abs, waves_per_cell, st2);
-  launch_class<512>(p, 3, k_abs, waves_per_cell, st);
+  launch_class<512>(p, 4, k_abs, waves_per_cell, st);
+  launch_class<384>(p, 3, k_abs, waves_per_cell, st);
   if (fork && (hipEventRecord(side.join, st2) != hipSuccess ||
                hipStreamWaitEvent(st, side.join, 0) != hipSuccess))
     return hipErrorUnknown;

@@ -115,11 +115,12 @@ def test_golovin_random_cells(B, orc, max_sd, seed, n_attr, boost):
 
 def test_golovin_tunings_same_result(B, orc):
     st = I.random_cells(64, 900, n_attr=1, rng_seed=9, p_boost=100.0)
-    for tu in [dict(wave_class_mask=8, waves_per_cell=1, big_bucket_target=32),
-               dict(wave_class_mask=15, waves_per_cell=8, big_bucket_target=1024),
-               dict(wave_class_mask=10, waves_per_cell=2, big_bucket_target=128),
-               dict(wave_class_mask=12, waves_per_cell=4, big_bucket_target=64, mid_max_slots=0),
-               dict(wave_class_mask=8, waves_per_cell=2, mid_max_slots=2048)]:
+    for tu in [dict(wave_class_mask=0x10, waves_per_cell=1, big_bucket_target=32),
+               dict(wave_class_mask=0x1F, waves_per_cell=8, big_bucket_target=1024),
+               dict(wave_class_mask=0x1A, waves_per_cell=2, big_bucket_target=128),
+               dict(wave_class_mask=0x14, waves_per_cell=4, big_bucket_target=64, mid_max_slots=0),
+               dict(wave_class_mask=0x18, waves_per_cell=2, mid_max_slots=2048),
+               dict(wave_class_mask=0x1C, waves_per_cell=1)]:
         say(f"tuning {tu}")
         assert _compare_run(B, orc, st, 6, tuning=tu, label=str(tu))
 
@@ -472,13 +473,15 @@ def _sub_state(st, cells):
     return idx, off
 
 
-def test_full_grid256_sampled_parity(B, orc):
+@pytest.mark.parametrize("mask", [0x10, 0x1C])
+def test_full_grid256_sampled_parity(B, orc, mask):
     """The benchmark's workload at full size (256 x 256 cells, 16.8 M SDs,
-    adaptive geometric, 6 attributes) in the benchmark's launch shape: one GPU
-    step, then the oracle recomputes a sample of cells one by one."""
+    adaptive geometric, 6 attributes) in the benchmark's launch shapes (one
+    class, or the 256/384/512-slot classes on two streams): one GPU step,
+    then the oracle recomputes a sample of cells one by one."""
     st = I.grid_256x256()
-    say(f"full 256x256 grid: {st.n_slots} slots")
-    g = GpuRun(B, st, tuning=dict(wave_class_mask=8, waves_per_cell=1))
+    say(f"full 256x256 grid: {st.n_slots} slots, class mask {mask:#x}")
+    g = GpuRun(B, st, tuning=dict(wave_class_mask=mask, waves_per_cell=1))
     g.step(1)
     xi, v, at = g.state()
     rng = np.random.default_rng(5)
