@@ -102,27 +102,66 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Wave-wide reductions and scans on DPP row operations (VALU lane moves)
+// and four readlanes, instead of LDS-routed shuffles: after the two quad
+// permutes, the half-row mirror and the row mirror every lane holds its
+// 16-lane row's result; lanes 15, 31, 47 and 63 then carry the four rows.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppQuad1032 = 0xB1;    // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuad2301 = 0x4E;    // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowMirror = 0x140;  // lane i <- lane 15 - i within a row
+constexpr int kDppHalfMirror = 0x141; // lane i <- lane 7 - i within a half row
+constexpr int kDppRowShr = 0x110;     // + n: lane i <- lane i - n within a row, 0 below
+
 __device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
+  x += dpp_i<kDppQuad1032>(x);
+  x += dpp_i<kDppQuad2301>(x);
+  x += dpp_i<kDppHalfMirror>(x);
+  x += dpp_i<kDppRowMirror>(x);
+  return __builtin_amdgcn_readlane(x, 15) + __builtin_amdgcn_readlane(x, 31) +
+         __builtin_amdgcn_readlane(x, 47) + __builtin_amdgcn_readlane(x, 63);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_i<CTRL>((int)(b & 0xFFFFFFFFll));
+  const int hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 __device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = fmax(x, __shfl_xor(x, d, 64));
-  return x;
+  x = fmax(x, dpp_d<kDppQuad1032>(x));
+  x = fmax(x, dpp_d<kDppQuad2301>(x));
+  x = fmax(x, dpp_d<kDppHalfMirror>(x));
+  x = fmax(x, dpp_d<kDppRowMirror>(x));
+  return fmax(fmax(readlane_d(x, 15), readlane_d(x, 31)),
+              fmax(readlane_d(x, 47), readlane_d(x, 63)));
 }
 
 // exclusive prefix sum over the 64 lanes
 __device__ __forceinline__ int wave_excl_scan(int x, int lane) {
-  int inc = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += t;
-  }
-  return inc - x;
+  int v = x;  // inclusive scan within each 16-lane row (shifts 1, 2, 4, 8) ...
+  v += dpp_i<kDppRowShr + 1>(v);
+  v += dpp_i<kDppRowShr + 2>(v);
+  v += dpp_i<kDppRowShr + 4>(v);
+  v += dpp_i<kDppRowShr + 8>(v);
+  // ... plus the totals of the rows before
+  const int r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31),
+            r2 = __builtin_amdgcn_readlane(v, 47);
+  const int row = lane >> 4;
+  v += row == 0 ? 0 : row == 1 ? r0 : row == 2 ? r0 + r1 : r0 + r1 + r2;
+  return v - x;
 }
 
 __device__ __forceinline__ void add_stats(unsigned long long* stats, unsigned long long live,
