@@ -175,10 +175,11 @@ __device__ __forceinline__ void add_stats(unsigned long long* stats, unsigned lo
 
 // ---------------------------------------------------------------------------
 // Update of one colliding pair.  ia/ib index xs/vs (LDS or global) and ga/gb
-// the global slots of the attributes.
+// the global slots of the attributes.  Returns 1 if a slot was left empty
+// (an equal split of a multiplicity-1 pair), else 0.
 // ---------------------------------------------------------------------------
 template <typename XI, typename VV>
-__device__ __forceinline__ void update_pair(XI* xs, VV* vs, int ia, int ib, long long xa,
+__device__ __forceinline__ int update_pair(XI* xs, VV* vs, int ia, int ib, long long xa,
                                             long long xb, double va, double vb, long long gamma,
                                             double* attrs, int64_t n_slots, int n_attr,
                                             int64_t ga, int64_t gb) {
@@ -201,6 +202,7 @@ __device__ __forceinline__ void update_pair(XI* xs, VV* vs, int ia, int ib, long
       double* a = attrs + (int64_t)q * n_slots;
       a[gk] = fma(gd, a[gj], a[gk]);
     }
+    return 0;
   } else {  // equal-multiplicity split
     const long long h = xk >> 1;
     xs[ij] = h;
@@ -214,6 +216,7 @@ __device__ __forceinline__ void update_pair(XI* xs, VV* vs, int ia, int ib, long
       a[gj] = ta;
       a[gk] = ta;
     }
+    return h == 0 ? 1 : 0;  // xk = 1: slot j is left empty
   }
 }
 
@@ -435,7 +438,8 @@ enum PassMode { kPassPlain = 0, kPassPmax = 1, kPassAdapt = 2 };
 template <int CAP, int W, int MODE>
 __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp, int n,
                                              int nlive, int tid, int c, uint32_t s, uint32_t u,
-                                             double q, bool clamp, int64_t o0, int* ncoll) {
+                                             double q, bool clamp, int64_t o0, int* ncoll,
+                                             int* ndead = nullptr) {
   constexpr int T = 64 * W;
   constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);
   const int P = nlive >> 1;
@@ -463,12 +467,16 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
       const int m = 2 * h + e;
       if (m >= P) break;
       const int a = aa[e], bb = bs[e];
-      const long long xa = L.xs[a], xb = L.xs[bb];
-      const double va = L.vs[a], vb = L.vs[bb];
+      long long xa = 0, xb = 0;
+      double va = 0.0, vb = 0.0;
       double p;
       if (MODE == kPassAdapt) {
-        p = pre[m] * q;
+        p = pre[m] * q;  // xi and v are read only for a collision
       } else {
+        xa = L.xs[a];
+        xb = L.xs[bb];
+        va = L.vs[a];
+        vb = L.vs[bb];
         const double kv = coal_kernel(kind, bgol, va, vb);
         const double pp = ((double)(xa > xb ? xa : xb) * kv) * S;
         if (MODE == kPassPmax) {
@@ -491,8 +499,12 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
           update_pair(dp->xi + o0, dp->v + o0, a, bb, xa, xb, va, vb, gamma, dp->attrs,
                       dp->n_slots, dp->n_attr, o0 + a, o0 + bb);
         } else {
-          update_pair(L.xs, L.vs, a, bb, xa, xb, va, vb, gamma, dp->attrs, dp->n_slots,
-                      dp->n_attr, o0 + a, o0 + bb);
+          xa = L.xs[a];
+          xb = L.xs[bb];
+          va = L.vs[a];
+          vb = L.vs[bb];
+          *ndead += update_pair(L.xs, L.vs, a, bb, xa, xb, va, vb, gamma, dp->attrs,
+                                dp->n_slots, dp->n_attr, o0 + a, o0 + bb);
           atomicOr(&L.dirty[a >> 5], 1u << (a & 31));
           atomicOr(&L.dirty[bb >> 5], 1u << (bb & 31));
         }
@@ -507,14 +519,6 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
   }
   team_sync<W>();
   return pmax;
-}
-
-template <int CAP, int W>
-__device__ __forceinline__ int team_count_live(CellLds<CAP>& L, int n, int tid, int lane,
-                                               int wv) {
-  int nl = 0;
-  for (int j = tid; j < n; j += 64 * W) nl += L.xs[j] > 0 ? 1 : 0;
-  return team_sum<W>(L, nl, lane, wv);
 }
 
 __device__ __forceinline__ void sink_clear_cell(const SimDesc* dp, int c, int n, int tid, int T) {
@@ -591,10 +595,10 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
     double dt_left = dp->dt;
     uint32_t u = 0;
     const uint32_t umax = (uint32_t)dp->max_substeps;
+    int nl = nlive;  // live SDs: a substep only empties slots by multiplicity-1 splits
     while (dt_left > 0.0) {
       const bool capped = u >= umax;
       if (capped && tid == 0) atomicOr(dp->status, kFlagSubstepCap);
-      const int nl = u == 0 ? nlive : team_count_live<CAP, W>(L, n, tid, lane, wv);
       if (nl < 2) {
         if (capped) {
           sink_clear_cell(dp, c, n, tid, T);
@@ -607,8 +611,10 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
                                                   false, o0, &ncoll);
       pmax = team_max<W>(L, pmax, lane, wv);
       const double dt_sub = (capped || pmax <= 1.0) ? dt_left : dt_left / pmax;
+      int ndead = 0;
       team_pairs<CAP, W, kPassAdapt>(L, dp, n, nl, tid, c, s, u, dt_sub / dv, !capped, o0,
-                                     &ncoll);
+                                     &ncoll, &ndead);
+      nl -= team_sum<W>(L, ndead, lane, wv);
       // the next substep's attribute loads come from this same workgroup: one
       // CU, one vector L1, so ordering the stores before them is all it takes
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
