@@ -7,15 +7,17 @@ sweep-out kernel, 6 extra fp64 extensive attributes, int64 multiplicities,
 per-cell adaptive substepping keeping gamma <= 1, a drizzle mode in a quarter
 of the cells.  Its state (1.07 GB) exceeds the GPU's last-level cache, so it
 is the one on which the HBM-roofline fraction means something.  One step is
-one outer coalescence step of every cell: a single fused launch.
+one outer coalescence step of every cell: one launch per populated cell-size
+class (the classes up to 256 slots on a second stream, concurrently).
 
 Inputs are synthetic and seeded (paper_2103_17238_amd.inputs), resident in HBM
 before timing starts.  The throughput unit is the super-droplet-step (one live
 SD through one outer step).  Algorithmic bytes per step: 16 per live SD
 (read xi and v), 8 per dead slot (read xi), (32 + 32 A) per colliding pair,
-8 per cell (offsets); see the design doc.
+8 per cell (offsets).
 
-Prints ONE JSON line.  --gpus above 1 is refused: this build measures one GPU.
+Prints ONE JSON line.  --gpus above 1 is refused: the benchmark measures one
+GPU.
 """
 import argparse
 import hashlib
@@ -124,6 +126,10 @@ def main():
     ap.add_argument("--workload", default="grid256",
                     choices=["grid256", "grid64", "golovin", "geometric", "serving"])
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--mask", type=lambda x: int(x, 0), default=None,
+                    help="fixed class mask (skips the autotuner; e.g. 0x18)")
+    ap.add_argument("--waves", type=int, default=None,
+                    help="fixed waves per cell (with --mask)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cells", type=int, default=65536)
     ap.add_argument("--cpu-steps", type=int, default=30)
@@ -137,7 +143,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(cells shard across GPUs with no exchange, see DESIGN.md)", file=sys.stderr)
+              "(cells would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -165,7 +171,20 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuning_note = "default"
-    if not args.no_tune:
+    if args.mask is not None:
+        t = B.sdm_get_tuning(sim.handle)
+        t.wave_class_mask = args.mask
+        t.waves_per_cell = args.waves if args.waves else t.waves_per_cell
+        B.sdm_set_tuning(sim.handle, t)
+        tuning_note = "fixed"
+    elif not args.no_tune and args.workload not in ("grid256", "grid64"):
+        # boxes: the library's autotuner (cell paths, bucket sizes) on a scratch copy
+        scratch = B.workspace_tensor(B.sdm_autotune_scratch_bytes(sim.handle))
+        t = B.sdm_autotune(sim.handle, scratch, trial_steps=3, stream=stream)
+        B.sdm_set_tuning(sim.handle, t)
+        del scratch
+        tuning_note = "autotuned"
+    elif not args.no_tune:
         # shapes: every cell in the 512-slot class (one launch per step), or
         # cells of <= 256 slots in their own class on a second stream (two
         # concurrent launches); waves per cell
