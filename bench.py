@@ -8,7 +8,8 @@ per-cell adaptive substepping keeping gamma <= 1, a drizzle mode in a quarter
 of the cells.  Its state (1.07 GB) exceeds the GPU's last-level cache, so it
 is the one on which the HBM-roofline fraction means something.  One step is
 one outer coalescence step of every cell: one launch per populated cell-size
-class (the classes up to 256 slots on a second stream, concurrently).
+class (the classes up to 256 slots and the mid-size cells on a second
+stream, concurrently).
 
 Inputs are synthetic and seeded (paper_2103_17238_amd.inputs), resident in HBM
 before timing starts.  The throughput unit is the super-droplet-step (one live

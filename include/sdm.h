@@ -94,7 +94,8 @@ typedef struct {
   int32_t wave_class_mask;   /* bit k (k = 0..4) enables the workgroup-per-cell class of
                                 64, 128, 256, 384, 512 slots; a cell goes to the smallest
                                 enabled class that fits; bit 4 (512) is always on.  Classes
-                                up to 256 slots run on a second stream beside the larger ones */
+                                up to 256 slots and the mid-size cells run on a second stream
+                                beside the larger classes and the big-cell kernels */
   int32_t waves_per_cell;    /* 1, 2, 4 or 8: wavefronts in the workgroup of one cell */
   int32_t big_bucket_target; /* cells on the big-cell path: expected SDs per sort bucket,
                                 32..1024 */

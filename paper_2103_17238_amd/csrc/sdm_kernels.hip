@@ -1319,10 +1319,14 @@ static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st
 
 hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st,
                        const SideStream& side) {
-  // cells of up to 256 slots run beside the 384- and 512-slot classes on a
-  // second stream: the launches fill each other's tails
-  const bool fork = side.stream && (p.n_wave[3] > 0 || p.n_wave[4] > 0) &&
-                    (p.n_wave[0] > 0 || p.n_wave[1] > 0 || p.n_wave[2] > 0);
+  // Two independent groups of launches run on two streams and fill each
+  // other's tails: the cells of up to 256 slots and the mid-size cells on a
+  // second stream, the 384- and 512-slot classes and the big-cell chain on
+  // the caller's stream (joined back through an event).
+  const bool small = p.n_wave[0] > 0 || p.n_wave[1] > 0 || p.n_wave[2] > 0;
+  const bool mid = p.n_mid[0] > 0 || p.n_mid[1] > 0 || p.n_mid[2] > 0 || p.n_mid[3] > 0;
+  const bool large = p.n_wave[3] > 0 || p.n_wave[4] > 0 || p.n_big > 0;
+  const bool fork = side.stream && (small || mid) && large;
   hipStream_t st2 = st;
   if (fork) {
     if (hipEventRecord(side.fork, st) != hipSuccess ||
@@ -1333,15 +1337,12 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hip
   launch_class<256>(p, 2, k_abs, waves_per_cell, st2);
   launch_class<128>(p, 1, k_abs, waves_per_cell, st2);
   launch_class<64>(p, 0, k_abs, waves_per_cell, st2);
+  launch_mid<16384>(p, 3, k_abs, st2);
+  launch_mid<8192>(p, 2, k_abs, st2);
+  launch_mid<4096>(p, 1, k_abs, st2);
+  launch_mid<2048>(p, 0, k_abs, st2);
   launch_class<512>(p, 4, k_abs, waves_per_cell, st);
   launch_class<384>(p, 3, k_abs, waves_per_cell, st);
-  if (fork && (hipEventRecord(side.join, st2) != hipSuccess ||
-               hipStreamWaitEvent(st, side.join, 0) != hipSuccess))
-    return hipErrorUnknown;
-  launch_mid<16384>(p, 3, k_abs, st);
-  launch_mid<8192>(p, 2, k_abs, st);
-  launch_mid<4096>(p, 1, k_abs, st);
-  launch_mid<2048>(p, 0, k_abs, st);
   if (p.n_big > 0) {
     hipLaunchKernelGGL(k_big_count, dim3(p.n_chunks), dim3(256), 0, st, p.desc, p.big, p.chunks,
                        p.bucket_cnt, p.task_live, k_abs);
@@ -1356,6 +1357,9 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hip
     hipLaunchKernelGGL(k_big_pairs, dim3(p.n_pblocks), dim3(256), 0, st, p.desc, p.big,
                        p.pblocks, p.task_nlive, p.ord, k_abs);
   }
+  if (fork && (hipEventRecord(side.join, st2) != hipSuccess ||
+               hipStreamWaitEvent(st, side.join, 0) != hipSuccess))
+    return hipErrorUnknown;
   return hipGetLastError();
 }
 
