@@ -1,0 +1,39 @@
+"""Host-side helpers of bench.py (no GPU): which cell classes a launch shape
+populates, and the committed HBM-traffic summary it reads."""
+import json
+import os
+
+import numpy as np
+
+import bench
+from paper_2103_17238_amd import inputs as I
+
+
+def test_launched_classes():
+    st = I.grid(4, 4, 100, max_sd=500, seed=1)
+    n = np.diff(st.cell_off)
+    caps = bench.launched_classes(st, 0x1F)
+    # every populated cell goes to the smallest enabled class that fits
+    want = sorted({min(c for c in bench.CLASS_CAPS if c >= x) for x in n if 0 < x <= 512})
+    assert caps == want
+    assert bench.launched_classes(st, 0x00) == [512]  # the 512-slot class is always on
+    assert set(bench.launched_classes(st, 0x18)) <= {384, 512}
+
+
+def test_traffic_summary_is_consistent():
+    path = os.path.join(bench.PROFILES, "k_cells_grid256_pmc.json")
+    d = json.load(open(path))
+    for key in ("kernel_source_sha", "fetch_kib_per_dispatch", "write_kib_per_dispatch",
+                "fetch_scale", "write_scale", "commands"):
+        assert key in d
+    assert abs(d["fetch_kib_per_dispatch"] - d["fetch_kib_per_dispatch_raw"] * d["fetch_scale"]) < 1
+    # the scale factors come from a 1 GiB copy: expected KiB / counted KiB
+    cp = d["copy_probe"]
+    assert abs(d["fetch_scale"] - cp["bytes"] / 1024 / cp["fetch_kib_raw"]) < 1e-9
+    assert abs(d["write_scale"] - cp["bytes"] / 1024 / cp["write_kib_raw"]) < 1e-9
+    # the traffic is only used while the kernel source matches the summary
+    got = bench.traffic_from_profiles("k_cells", "grid256", 0)
+    if d["kernel_source_sha"] == bench.kernel_source_sha():
+        assert got == (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0
+    else:
+        assert got is None

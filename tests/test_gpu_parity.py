@@ -358,13 +358,16 @@ def test_step_limit(B, orc):
 
 def test_batch_equals_separate(B, orc):
     """Shared launches over several simulations of different kernels, sizes,
-    seeds and modes give each one exactly its solo result."""
+    seeds and modes give each one exactly its solo result.  The batch has
+    cells in the small and large workgroup-per-cell classes, mid-size cells
+    and one big cell, so every group of launches runs, on both streams."""
     import torch
 
     states = [I.random_cells(12, 300, n_attr=2, rng_seed=71, p_boost=30.0),
               I.golovin_box(2 ** 12, seed=5),
               I.geometric_box(2 ** 11, seed=9),
-              I.grid(8, 8, 128, max_sd=200, n_attr=3, kernel=I.GEOMETRIC, seed=3)]
+              I.grid(8, 8, 128, max_sd=200, n_attr=3, kernel=I.GEOMETRIC, seed=3),
+              I.golovin_box(2 ** 15, seed=13)]
     states[3].adaptive = True
     solo = []
     for st in states:
