@@ -119,6 +119,75 @@ def cpu_baseline(state, n_cells_sample, steps):
                       f"{steps} steps, OpenMP over cells; {dt:.1f} s"}
 
 
+def copy_bandwidth_gbs(gib=1.0, reps=5):
+    """Measured device-to-device copy bandwidth (read + write bytes over the
+    median copy time): a second, attainable denominator for the roofline."""
+    import numpy as np
+    import torch
+
+    n = int(gib * 2 ** 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    return 2 * n * 8 / float(np.median(times)) / 1e9
+
+
+def batched_vs_separate(state, tuning, n_cells=256, steps=5):
+    """The first n_cells cells of the workload as one simulation (one launch
+    per step and class) against the same cells as n_cells simulations of one
+    cell each (their own launches), same launch shape; SD-steps/s of both."""
+    import torch
+
+    from paper_2103_17238_amd import binding as B
+    from paper_2103_17238_amd import inputs as I
+
+    C = min(n_cells, state.n_cells)
+
+    def sub(c0, c1):
+        a, b = int(state.cell_off[c0]), int(state.cell_off[c1])
+        return I.State(state.xi[a:b].copy(), state.v[a:b].copy(),
+                       state.attrs[:, a:b].copy(), state.cell_off[c0:c1 + 1] - a,
+                       state.dt, state.dv, state.kernel, state.b, state.adaptive, state.seed)
+
+    def timed(sims):
+        for s in sims:
+            t = B.sdm_get_tuning(s.handle)
+            t.wave_class_mask, t.waves_per_cell = tuning["wave_class_mask"], tuning["waves_per_cell"]
+            B.sdm_set_tuning(s.handle, t)
+            s.step(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            for s in sims:
+                s.step(1)
+        e1.record()
+        torch.cuda.synchronize()
+        live = sum(B.sdm_stats(s.handle)["live_sd_steps"] for s in sims)
+        per_step = live / (steps + 1)
+        return per_step * steps / (e0.elapsed_time(e1) / 1e3)
+
+    one = [B.Sim(sub(0, C))]
+    batched = timed(one)
+    for s in one:
+        s.close()
+    many = [B.Sim(sub(c, c + 1)) for c in range(C)]
+    separate = timed(many)
+    for s in many:
+        s.close()
+    return {"cells": C, "steps": steps, "batched_sd_steps_per_s": batched,
+            "separate_sd_steps_per_s": separate, "speedup": batched / separate}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +201,8 @@ def main():
     ap.add_argument("--waves", type=int, default=None,
                     help="fixed waves per cell (with --mask)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batching-check", action="store_true",
+                    help="skip the batched-vs-separate comparison on a sample of cells")
     ap.add_argument("--cpu-cells", type=int, default=65536)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -230,6 +301,7 @@ def main():
     t_wall = time.perf_counter() - t_wall
     per_launch_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(K)])
     total_ms = float(evs[0].elapsed_time(evs[K]))
+    copy_gbs = copy_bandwidth_gbs()
     stats = B.sdm_stats(sim.handle)
     flags = B.sdm_status_word(sim.handle)
 
@@ -284,12 +356,17 @@ def main():
             "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes / K,
             "avg_launch_ms": float(per_launch_ms.mean()),
+            "median_launch_ms": float(np.median(per_launch_ms)),
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
         "stats": {"live_sd_steps": live, "colliding_pairs": coll,
                   "cell_substeps": stats["cell_substeps"], "cell_steps": stats["cell_steps"],
                   "status_flags": flags, "wall_s": t_wall},
     }
     sim.close()
+    if cell_grid and not args.no_batching_check:
+        line["batching"] = batched_vs_separate(host_state, tuning)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(host_state, args.cpu_cells, args.cpu_steps)
     else:
