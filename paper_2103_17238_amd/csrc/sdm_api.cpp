@@ -172,8 +172,10 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
 }
 
 struct Layout {
-  size_t desc, wave[sdm::kNumClasses], mid[sdm::kNumMid], big, chunks, buckets, pblocks, bucket_cnt, bucket_start,
-      task_live, task_nlive, tmp, ord, total;
+  size_t desc, wave[sdm::kNumClasses], wave_alt[sdm::kNumClasses], order_flag[sdm::kNumClasses],
+      order_cnt[sdm::kNumClasses],
+      mid[sdm::kNumMid], big, chunks, buckets, pblocks, bucket_cnt, bucket_start, task_live,
+      task_nlive, tmp, ord, total;
 };
 
 static Layout layout_of(int n_members, const Tables& T) {
@@ -185,8 +187,13 @@ static Layout layout_of(int n_members, const Tables& T) {
     return at;
   };
   L.desc = take(sizeof(SimDesc) * std::max(n_members, 1));
-  for (int k = 0; k < sdm::kNumClasses; ++k)
+  for (int k = 0; k < sdm::kNumClasses; ++k) {
+    const size_t na = T.wave[k].size() - (size_t)T.n_plain[k];
     L.wave[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(T.wave[k].size(), 1));
+    L.wave_alt[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(na, 1));
+    L.order_flag[k] = take(sizeof(uint32_t) * std::max<size_t>(na, 1));
+    L.order_cnt[k] = take(sizeof(uint32_t) * (na / sdm::kOrderBlock + 1));
+  }
   for (int k = 0; k < sdm::kNumMid; ++k)
     L.mid[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(T.mid[k].size(), 1));
   L.big = take(sizeof(BigTask) * std::max<size_t>(T.big.size(), 1));
@@ -219,7 +226,7 @@ static size_t plan_bytes_worst(const std::vector<sdm_sim*>& ms) {
       n_mid += (n > sdm::kWaveCapMax && n <= sdm::kMidCapMax) ? 1 : 0;
     }
   return layout_of((int)ms.size(), T).total + align_up(sizeof(sdm::CellTask) * n_mid) +
-         (sdm::kNumClasses + sdm::kNumMid) * kAlign;
+         (4 * sdm::kNumClasses + sdm::kNumMid) * kAlign;
 }
 
 struct Plan {
@@ -231,6 +238,7 @@ struct Plan {
   PlanDev dev{};
   std::vector<SimDesc> desc;  // host copy of the device descriptors
   uint32_t counter = 0;       // launch step of the next step
+  uint32_t flip = 0;          // steps launched since the tables were built
   sdm::SideStream side;       // created at the first step
   Plan() = default;
   Plan(const Plan&) = delete;
@@ -310,7 +318,10 @@ static sdm_status plan_setup(Plan* p, hipStream_t st) {
   for (auto* s : p->members) d.geo |= (s->cfg.kernel == SDM_GEOMETRIC) ? 1 : 0;
   d.desc = reinterpret_cast<const SimDesc*>(w + L.desc);
   for (int k = 0; k < sdm::kNumClasses; ++k) {
-    d.wave_tasks[k] = reinterpret_cast<const sdm::CellTask*>(w + L.wave[k]);
+    d.wave_tasks[k] = reinterpret_cast<sdm::CellTask*>(w + L.wave[k]);
+    d.wave_alt[k] = reinterpret_cast<sdm::CellTask*>(w + L.wave_alt[k]);
+    d.order_flag[k] = reinterpret_cast<uint32_t*>(w + L.order_flag[k]);
+    d.order_cnt[k] = reinterpret_cast<uint32_t*>(w + L.order_cnt[k]);
     d.n_wave[k] = (int)p->T.wave[k].size();
     d.n_plain[k] = p->T.n_plain[k];
   }
@@ -338,8 +349,14 @@ static sdm_status plan_setup(Plan* p, hipStream_t st) {
   p->desc.clear();
   for (auto* s : p->members) p->desc.push_back(make_desc(s, s->step - p->counter));
   HIP_TRY(upload(const_cast<SimDesc*>(d.desc), p->desc));
-  for (int k = 0; k < sdm::kNumClasses; ++k)
-    HIP_TRY(upload(const_cast<sdm::CellTask*>(d.wave_tasks[k]), p->T.wave[k]));
+  for (int k = 0; k < sdm::kNumClasses; ++k) {
+    HIP_TRY(upload(d.wave_tasks[k], p->T.wave[k]));
+    const size_t na = p->T.wave[k].size() - (size_t)p->T.n_plain[k];
+    if (na > 0)
+      HIP_TRY(hipMemcpy(d.wave_alt[k], p->T.wave[k].data() + p->T.n_plain[k],
+                        sizeof(sdm::CellTask) * na, hipMemcpyHostToDevice));
+    p->flip = 0;
+  }
   for (int k = 0; k < sdm::kNumMid; ++k)
     HIP_TRY(upload(const_cast<sdm::CellTask*>(d.mid_tasks[k]), p->T.mid[k]));
   HIP_TRY(upload(const_cast<BigTask*>(d.big), p->T.big));
@@ -389,8 +406,8 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
     }
   }
   for (int64_t k = 0; k < active; ++k) {
-    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->tuning.waves_per_cell, st,
-                         p->side) != hipSuccess)
+    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->flip++, p->tuning.waves_per_cell,
+                         st, p->side) != hipSuccess)
       return SDM_EDEVICE;
   }
   p->counter += (uint32_t)n_steps;
@@ -449,6 +466,11 @@ static size_t plan_bytes_bound(const sdm_config* c) {
   take(sizeof(SimDesc));
   for (int k = 0; k < sdm::kNumClasses + sdm::kNumMid; ++k)
     take(sizeof(sdm::CellTask) * (size_t)std::max<int64_t>(C, 1));
+  for (int k = 0; k < sdm::kNumClasses; ++k) {  // second lists, order flags and counts
+    take(sizeof(sdm::CellTask) * (size_t)std::max<int64_t>(C, 1));
+    take(sizeof(uint32_t) * (size_t)std::max<int64_t>(C, 1));
+    take(sizeof(uint32_t) * (size_t)(C / sdm::kOrderBlock + 1));
+  }
   take(sizeof(BigTask) * (size_t)std::max<int64_t>(nbig, 1));
   take(sizeof(BigChunk) * (size_t)(ns / sdm::kChunk + nbig + 1));
   const int64_t nbk = ns / (sdm::kMinBucketTarget / 2) + 2 * nbig + 1;

@@ -16,6 +16,7 @@ constexpr int kMidCapMax = 16384;
 constexpr int kChunk = 1024;      // slots per block in the big-cell key passes
 constexpr int kBucketCap = 1024;  // big-cell bucket entries staged in LDS by one wave
 constexpr int kMinBucketTarget = 32;
+constexpr int kOrderBlock = 1024;  // tasks per block of the dispatch-order partition
 
 constexpr uint32_t kFlagSubstepCap = 1u;
 constexpr uint32_t kFlagGammaCap = 2u;
@@ -92,7 +93,14 @@ struct BigPairBlock {  // 256 pair groups (4 sorted positions each) of one big c
 struct PlanDev {
   const SimDesc* desc;
   int geo;  // 1 if any member uses the geometric kernel
-  const CellTask* wave_tasks[kNumClasses];  // per class: plain-mode cells first, then adaptive
+  CellTask* wave_tasks[kNumClasses];  // per class: plain-mode cells first, then adaptive
+  // adaptive cells of each class: a second copy of their task list; each
+  // step writes the next step's order into the other list (cells that took
+  // several substeps first, a stable partition), the lists alternating from
+  // step to step; per task a flag, per 1024 tasks a count
+  CellTask* wave_alt[kNumClasses];
+  uint32_t* order_flag[kNumClasses];
+  uint32_t* order_cnt[kNumClasses];
   int n_wave[kNumClasses];
   int n_plain[kNumClasses];
   const CellTask* mid_tasks[kNumMid];  // per mid class: plain-mode cells first
@@ -121,8 +129,10 @@ struct SideStream {
 };
 
 // launches (sdm_kernels.hip)
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st,
-                       const SideStream& side);
+// flip: count of steps launched on this plan since its tables were built
+// (selects which of the two adaptive task lists a step reads)
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int waves_per_cell,
+                       hipStream_t st, const SideStream& side);
 hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
                           double* attr_sums, const double* edges, int n_bins, double* spectrum,
                           hipStream_t st);

@@ -537,7 +537,8 @@ __device__ __forceinline__ void sink_clear_cell(const SimDesc* dp, int c, int n,
 template <int CAP, int W, bool ADAPT>
 __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ descs,
                                                   const CellTask* __restrict__ tasks,
-                                                  uint32_t k_abs) {
+                                                  uint32_t k_abs,
+                                                  uint32_t* __restrict__ order_flag) {
   constexpr int T = 64 * W;
   constexpr int IT = (CAP + T - 1) / T;
   __shared__ CellLds<CAP> L;
@@ -563,7 +564,10 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
   const SimDesc* dp = descs + cur.sim;
   const int64_t o0 = cur.xi - dp->xi;
   const uint32_t s = k_abs + dp->step_delta;
-  if (s >= dp->step_limit) return;  // uniform over the block
+  if (s >= dp->step_limit) {  // uniform over the block
+    if (ADAPT && tid == 0) order_flag[blockIdx.x] = 0;
+    return;
+  }
   if (ADAPT)
     for (int k = tid; k < CAP / 32; k += T) L.dirty[k] = 0;
   int mylive = 0;
@@ -625,6 +629,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
     }
     if (u == 0) sink_clear_cell(dp, c, n, tid, T);
     nsub = (int)u;
+    if (tid == 0) order_flag[blockIdx.x] = u > 1 ? 1u : 0u;  // next step's dispatch order
     team_sync<W>();
     // write back the slots that changed
     for (int j = tid; j < n; j += T) {
@@ -1236,6 +1241,74 @@ __global__ void k_kernel_values(int kind, double b, const double* v1, const doub
 }
 
 // ---------------------------------------------------------------------------
+// Dispatch order of the adaptive cells of a class for the next step: a stable
+// partition of this step's list, cells that took more than one substep
+// first, so that the long cells start early instead of stretching the end of
+// the launch (results do not depend on the order).  k_order_count counts the
+// flagged tasks of each block of kOrderBlock; k_order_scatter places every
+// task from the counts of the blocks before it and its rank in its block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_excl_count(bool pred, int tid, uint32_t* red,
+                                                     uint32_t* total) {
+  const int lane = tid & 63, wv = tid >> 6;
+  const unsigned long long m = __ballot(pred);
+  const uint32_t in_wave = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) red[wv] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kOrderBlock / 64; ++k) {
+    const uint32_t c = red[k];
+    before += k < wv ? c : 0u;
+    all += c;
+  }
+  *total = all;
+  return before + in_wave;
+}
+
+__global__ void __launch_bounds__(kOrderBlock) k_order_count(const uint32_t* __restrict__ flag,
+                                                             uint32_t* __restrict__ cnt, int n) {
+  __shared__ uint32_t red[kOrderBlock / 64];
+  const int i = blockIdx.x * kOrderBlock + threadIdx.x;
+  uint32_t total;
+  (void)block_excl_count(i < n && flag[i] != 0u, threadIdx.x, red, &total);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kOrderBlock) k_order_scatter(
+    const CellTask* __restrict__ in, const uint32_t* __restrict__ flag,
+    const uint32_t* __restrict__ cnt, CellTask* __restrict__ out, int n, int nblocks) {
+  __shared__ uint32_t red[kOrderBlock / 64];
+  __shared__ uint32_t pre[2];
+  const int tid = threadIdx.x;
+  if (tid < 64) {  // flagged tasks in the blocks before this one, and in all
+    uint32_t b = 0, a = 0;
+    for (int k = tid; k < nblocks; k += 64) {
+      const uint32_t c = cnt[k];
+      b += k < (int)blockIdx.x ? c : 0u;
+      a += c;
+    }
+    b = (uint32_t)wave_sum((int)b);
+    a = (uint32_t)wave_sum((int)a);
+    if (tid == 0) {
+      pre[0] = b;
+      pre[1] = a;
+    }
+  }
+  __syncthreads();
+  const int i = blockIdx.x * kOrderBlock + tid;
+  const bool ok = i < n;
+  const bool heavy = ok && flag[i] != 0u;
+  uint32_t total;
+  const uint32_t r = block_excl_count(heavy, tid, red, &total);  // flagged before, in block
+  if (!ok) return;
+  const uint32_t heavy_before = pre[0], heavy_all = pre[1];
+  const uint32_t pos = heavy ? heavy_before + r
+                             : heavy_all + ((uint32_t)i - heavy_before - r);  // lights before
+  out[pos] = in[i];
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 size_t cell_lds_bytes(int cls) {
@@ -1275,23 +1348,35 @@ void set_lds_limits() {
 }
 
 template <int CAP, int W>
-static void launch_class_w(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st) {
+static void launch_class_w(const PlanDev& p, int cls, uint32_t k_abs, uint32_t flip,
+                           hipStream_t st) {
   const int np = p.n_plain[cls], na = p.n_wave[cls] - p.n_plain[cls];
   if (np > 0)
     hipLaunchKernelGGL((k_cells<CAP, W, false>), dim3(np), dim3(64 * W), 0, st, p.desc,
-                       p.wave_tasks[cls], k_abs);
-  if (na > 0)
-    hipLaunchKernelGGL((k_cells<CAP, W, true>), dim3(na), dim3(64 * W), 0, st, p.desc,
-                       p.wave_tasks[cls] + np, k_abs);
+                       p.wave_tasks[cls], k_abs, nullptr);
+  if (na > 0) {
+    // the adaptive list of this step, and the one the next step will use
+    const uint32_t par = flip & 1u;
+    CellTask* cur = par ? p.wave_alt[cls] : p.wave_tasks[cls] + np;
+    CellTask* nxt = par ? p.wave_tasks[cls] + np : p.wave_alt[cls];
+    hipLaunchKernelGGL((k_cells<CAP, W, true>), dim3(na), dim3(64 * W), 0, st, p.desc, cur,
+                       k_abs, p.order_flag[cls]);
+    const int nb = (na + kOrderBlock - 1) / kOrderBlock;
+    hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(kOrderBlock), 0, st, p.order_flag[cls],
+                       p.order_cnt[cls], na);
+    hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(kOrderBlock), 0, st, cur,
+                       p.order_flag[cls], p.order_cnt[cls], nxt, na, nb);
+  }
 }
 
 template <int CAP>
-static void launch_class(const PlanDev& p, int cls, uint32_t k_abs, int w, hipStream_t st) {
+static void launch_class(const PlanDev& p, int cls, uint32_t k_abs, uint32_t flip, int w,
+                         hipStream_t st) {
   switch (w) {
-    case 1: launch_class_w<CAP, 1>(p, cls, k_abs, st); break;
-    case 2: launch_class_w<CAP, 2>(p, cls, k_abs, st); break;
-    case 4: launch_class_w<CAP, 4>(p, cls, k_abs, st); break;
-    default: launch_class_w<CAP, 8>(p, cls, k_abs, st); break;
+    case 1: launch_class_w<CAP, 1>(p, cls, k_abs, flip, st); break;
+    case 2: launch_class_w<CAP, 2>(p, cls, k_abs, flip, st); break;
+    case 4: launch_class_w<CAP, 4>(p, cls, k_abs, flip, st); break;
+    default: launch_class_w<CAP, 8>(p, cls, k_abs, flip, st); break;
   }
 }
 
@@ -1317,8 +1402,8 @@ static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st
                        p.mid_tasks[cls] + np, k_abs);
 }
 
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hipStream_t st,
-                       const SideStream& side) {
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int waves_per_cell,
+                       hipStream_t st, const SideStream& side) {
   // Two independent groups of launches run on two streams and fill each
   // other's tails: the cells of up to 256 slots and the mid-size cells on a
   // second stream, the 384- and 512-slot classes and the big-cell chain on
@@ -1334,15 +1419,15 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, int waves_per_cell, hip
       return hipErrorUnknown;
     st2 = side.stream;
   }
-  launch_class<256>(p, 2, k_abs, waves_per_cell, st2);
-  launch_class<128>(p, 1, k_abs, waves_per_cell, st2);
-  launch_class<64>(p, 0, k_abs, waves_per_cell, st2);
+  launch_class<256>(p, 2, k_abs, flip, waves_per_cell, st2);
+  launch_class<128>(p, 1, k_abs, flip, waves_per_cell, st2);
+  launch_class<64>(p, 0, k_abs, flip, waves_per_cell, st2);
   launch_mid<16384>(p, 3, k_abs, st2);
   launch_mid<8192>(p, 2, k_abs, st2);
   launch_mid<4096>(p, 1, k_abs, st2);
   launch_mid<2048>(p, 0, k_abs, st2);
-  launch_class<512>(p, 4, k_abs, waves_per_cell, st);
-  launch_class<384>(p, 3, k_abs, waves_per_cell, st);
+  launch_class<512>(p, 4, k_abs, flip, waves_per_cell, st);
+  launch_class<384>(p, 3, k_abs, flip, waves_per_cell, st);
   if (p.n_big > 0) {
     hipLaunchKernelGGL(k_big_count, dim3(p.n_chunks), dim3(256), 0, st, p.desc, p.big, p.chunks,
                        p.bucket_cnt, p.task_live, k_abs);
