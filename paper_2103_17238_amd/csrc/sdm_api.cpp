@@ -192,7 +192,7 @@ static Layout layout_of(int n_members, const Tables& T) {
     L.wave[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(T.wave[k].size(), 1));
     L.wave_alt[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(na, 1));
     L.order_flag[k] = take(sizeof(uint32_t) * std::max<size_t>(na, 1));
-    L.order_cnt[k] = take(sizeof(uint32_t) * (na / sdm::kOrderBlock + 1));
+    L.order_cnt[k] = take(sizeof(uint32_t) * sdm::kOrderGroups * (na / sdm::kOrderBlock + 1));
   }
   for (int k = 0; k < sdm::kNumMid; ++k)
     L.mid[k] = take(sizeof(sdm::CellTask) * std::max<size_t>(T.mid[k].size(), 1));
@@ -469,7 +469,7 @@ static size_t plan_bytes_bound(const sdm_config* c) {
   for (int k = 0; k < sdm::kNumClasses; ++k) {  // second lists, order flags and counts
     take(sizeof(sdm::CellTask) * (size_t)std::max<int64_t>(C, 1));
     take(sizeof(uint32_t) * (size_t)std::max<int64_t>(C, 1));
-    take(sizeof(uint32_t) * (size_t)(C / sdm::kOrderBlock + 1));
+    take(sizeof(uint32_t) * sdm::kOrderGroups * (size_t)(C / sdm::kOrderBlock + 1));
   }
   take(sizeof(BigTask) * (size_t)std::max<int64_t>(nbig, 1));
   take(sizeof(BigChunk) * (size_t)(ns / sdm::kChunk + nbig + 1));

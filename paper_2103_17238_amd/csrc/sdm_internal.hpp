@@ -17,6 +17,7 @@ constexpr int kChunk = 1024;      // slots per block in the big-cell key passes
 constexpr int kBucketCap = 1024;  // big-cell bucket entries staged in LDS by one wave
 constexpr int kMinBucketTarget = 32;
 constexpr int kOrderBlock = 1024;  // tasks per block of the dispatch-order partition
+constexpr int kOrderGroups = 4;    // dispatch-order groups by substeps taken
 
 constexpr uint32_t kFlagSubstepCap = 1u;
 constexpr uint32_t kFlagGammaCap = 2u;
@@ -95,9 +96,9 @@ struct PlanDev {
   int geo;  // 1 if any member uses the geometric kernel
   CellTask* wave_tasks[kNumClasses];  // per class: plain-mode cells first, then adaptive
   // adaptive cells of each class: a second copy of their task list; each
-  // step writes the next step's order into the other list (cells that took
-  // several substeps first, a stable partition), the lists alternating from
-  // step to step; per task a flag, per 1024 tasks a count
+  // step writes the next step's order into the other list (a stable
+  // partition by substeps taken, most first), the lists alternating from step
+  // to step; per task its group, per block of tasks a count per group
   CellTask* wave_alt[kNumClasses];
   uint32_t* order_flag[kNumClasses];
   uint32_t* order_cnt[kNumClasses];

@@ -220,6 +220,12 @@ __device__ __forceinline__ int update_pair(XI* xs, VV* vs, int ia, int ib, long 
   }
 }
 
+// Dispatch-order group of an adaptive cell by the substeps it took (8 or
+// more, 4-7, 2-3, at most 1): the next step dispatches the groups in order.
+__device__ __forceinline__ uint32_t order_group(uint32_t substeps) {
+  return substeps >= 8 ? 0u : substeps >= 4 ? 1u : substeps >= 2 ? 2u : 3u;
+}
+
 // A thread's share of the bucket-counter scan: `per` consecutive counters
 // from `first` (16-byte LDS accesses when per is a multiple of 4).
 __device__ __forceinline__ int scan_load(const uint32_t* cnt, int first, int per, int nb) {
@@ -565,7 +571,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
   const int64_t o0 = cur.xi - dp->xi;
   const uint32_t s = k_abs + dp->step_delta;
   if (s >= dp->step_limit) {  // uniform over the block
-    if (ADAPT && tid == 0) order_flag[blockIdx.x] = 0;
+    if (ADAPT && tid == 0) order_flag[blockIdx.x] = order_group(0);
     return;
   }
   if (ADAPT)
@@ -629,7 +635,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
     }
     if (u == 0) sink_clear_cell(dp, c, n, tid, T);
     nsub = (int)u;
-    if (tid == 0) order_flag[blockIdx.x] = u > 1 ? 1u : 0u;  // next step's dispatch order
+    if (tid == 0) order_flag[blockIdx.x] = order_group(u);  // next step's dispatch order
     team_sync<W>();
     // write back the slots that changed
     for (int j = tid; j < n; j += T) {
@@ -1242,12 +1248,15 @@ __global__ void k_kernel_values(int kind, double b, const double* v1, const doub
 
 // ---------------------------------------------------------------------------
 // Dispatch order of the adaptive cells of a class for the next step: a stable
-// partition of this step's list, cells that took more than one substep
-// first, so that the long cells start early instead of stretching the end of
-// the launch (results do not depend on the order).  k_order_count counts the
-// flagged tasks of each block of kOrderBlock; k_order_scatter places every
-// task from the counts of the blocks before it and its rank in its block.
+// partition of this step's list into kOrderGroups groups by the substeps each
+// cell took (8 or more, 4-7, 2-3, at most 1), longest first, so that the long
+// cells start early instead of stretching the end of the launch (results do
+// not depend on the order).  k_order_count counts each group in each block of
+// kOrderBlock tasks; k_order_scatter places every task from the counts of the
+// groups and blocks before it and its rank among its group in its block.
 // ---------------------------------------------------------------------------
+// exclusive count of pred over the block's threads before this one; *total:
+// over the whole block
 __device__ __forceinline__ uint32_t block_excl_count(bool pred, int tid, uint32_t* red,
                                                      uint32_t* total) {
   const int lane = tid & 63, wv = tid >> 6;
@@ -1262,50 +1271,61 @@ __device__ __forceinline__ uint32_t block_excl_count(bool pred, int tid, uint32_
     before += k < wv ? c : 0u;
     all += c;
   }
+  __syncthreads();  // red is reused by the next call
   *total = all;
   return before + in_wave;
 }
 
-__global__ void __launch_bounds__(kOrderBlock) k_order_count(const uint32_t* __restrict__ flag,
+__global__ void __launch_bounds__(kOrderBlock) k_order_count(const uint32_t* __restrict__ group,
                                                              uint32_t* __restrict__ cnt, int n) {
   __shared__ uint32_t red[kOrderBlock / 64];
   const int i = blockIdx.x * kOrderBlock + threadIdx.x;
-  uint32_t total;
-  (void)block_excl_count(i < n && flag[i] != 0u, threadIdx.x, red, &total);
-  if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+  const uint32_t g = i < n ? group[i] : kOrderGroups;
+#pragma unroll
+  for (int q = 0; q < kOrderGroups; ++q) {
+    uint32_t total;
+    (void)block_excl_count(g == (uint32_t)q, threadIdx.x, red, &total);
+    if (threadIdx.x == 0) cnt[blockIdx.x * kOrderGroups + q] = total;
+  }
 }
 
 __global__ void __launch_bounds__(kOrderBlock) k_order_scatter(
-    const CellTask* __restrict__ in, const uint32_t* __restrict__ flag,
+    const CellTask* __restrict__ in, const uint32_t* __restrict__ group,
     const uint32_t* __restrict__ cnt, CellTask* __restrict__ out, int n, int nblocks) {
   __shared__ uint32_t red[kOrderBlock / 64];
-  __shared__ uint32_t pre[2];
+  __shared__ uint32_t base[kOrderGroups];  // first slot of the group's tasks of this block
   const int tid = threadIdx.x;
-  if (tid < 64) {  // flagged tasks in the blocks before this one, and in all
-    uint32_t b = 0, a = 0;
-    for (int k = tid; k < nblocks; k += 64) {
-      const uint32_t c = cnt[k];
-      b += k < (int)blockIdx.x ? c : 0u;
-      a += c;
-    }
-    b = (uint32_t)wave_sum((int)b);
-    a = (uint32_t)wave_sum((int)a);
-    if (tid == 0) {
-      pre[0] = b;
-      pre[1] = a;
+  if (tid < 64) {
+    uint32_t before[kOrderGroups], all[kOrderGroups];
+#pragma unroll
+    for (int q = 0; q < kOrderGroups; ++q) before[q] = all[q] = 0;
+    for (int b = tid; b < nblocks; b += 64)
+#pragma unroll
+      for (int q = 0; q < kOrderGroups; ++q) {
+        const uint32_t c = cnt[b * kOrderGroups + q];
+        before[q] += b < (int)blockIdx.x ? c : 0u;
+        all[q] += c;
+      }
+    uint32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < kOrderGroups; ++q) {
+      const uint32_t bq = (uint32_t)wave_sum((int)before[q]);
+      const uint32_t aq = (uint32_t)wave_sum((int)all[q]);
+      if (tid == 0) base[q] = run + bq;
+      run += aq;
     }
   }
   __syncthreads();
   const int i = blockIdx.x * kOrderBlock + tid;
-  const bool ok = i < n;
-  const bool heavy = ok && flag[i] != 0u;
-  uint32_t total;
-  const uint32_t r = block_excl_count(heavy, tid, red, &total);  // flagged before, in block
-  if (!ok) return;
-  const uint32_t heavy_before = pre[0], heavy_all = pre[1];
-  const uint32_t pos = heavy ? heavy_before + r
-                             : heavy_all + ((uint32_t)i - heavy_before - r);  // lights before
-  out[pos] = in[i];
+  const uint32_t g = i < n ? group[i] : kOrderGroups;
+  uint32_t pos = 0;
+#pragma unroll
+  for (int q = 0; q < kOrderGroups; ++q) {
+    uint32_t total;
+    const uint32_t r = block_excl_count(g == (uint32_t)q, tid, red, &total);
+    if (g == (uint32_t)q) pos = base[q] + r;
+  }
+  if (i < n) out[pos] = in[i];
 }
 
 // ---------------------------------------------------------------------------
