@@ -72,9 +72,10 @@ def launched_classes(state, mask):
     return used
 
 
-def traffic_from_profiles(kernel_name, workload, launches_bytes):
-    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
-    were taken on the current kernel source; else None."""
+def traffic_from_profiles(kernel_name, workload, launches_bytes, tuning=None):
+    """HBM bytes per step (all launches of the step) from committed rocprofv3
+    --pmc summaries, if they were taken on the current kernel source in the
+    same launch shape; else None."""
     path = os.path.join(PROFILES, f"{kernel_name}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
@@ -82,13 +83,13 @@ def traffic_from_profiles(kernel_name, workload, launches_bytes):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha") != kernel_source_sha():
+    if d.get("kernel_source_sha") != kernel_source_sha() or tuning is None:
         return None
-    # KiB per step (the step's cell launches) or per dispatch, already scaled
-    # by the copy probe (see the json's commands)
-    if "fetch_kib_per_step" in d:
-        return (d["fetch_kib_per_step"] + d["write_kib_per_step"]) * 1024.0
-    return (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0
+    shape = d.get("shapes", {}).get(f"{tuning['wave_class_mask']:#x}/{tuning['waves_per_cell']}")
+    if shape is None:
+        return None
+    # KiB per step, already scaled by the copy probe (see the json's commands)
+    return (shape["fetch_kib_per_step"] + shape["write_kib_per_step"]) * 1024.0
 
 
 def cpu_baseline(state, n_cells_sample, steps):
@@ -260,7 +261,7 @@ def main():
         # shapes: every cell in the 512-slot class (one launch per step), or
         # cells of <= 256 slots in their own class on a second stream (two
         # concurrent launches); waves per cell
-        best = None
+        trials = []
         for mask in (0x10, 0x14, 0x18, 0x1C):
             for wpb in (1, 2):
                 t = B.sdm_get_tuning(sim.handle)
@@ -276,10 +277,10 @@ def main():
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / 4
                 probe.close()
-                if best is None or ms < best[0]:
-                    best = (ms, mask, wpb)
+                trials.append((ms, len(launched_classes(state, mask)), mask, wpb))
+        best = min(trials)
         t = B.sdm_get_tuning(sim.handle)
-        t.wave_class_mask, t.waves_per_cell = best[1], best[2]
+        t.wave_class_mask, t.waves_per_cell = best[2], best[3]
         B.sdm_set_tuning(sim.handle, t)
         tuning_note = "autotuned"
     tuning = B.sdm_get_tuning(sim.handle).as_dict()
@@ -320,7 +321,7 @@ def main():
     else:  # the step's cell launches (concurrent when there are several)
         kernel_name = " || ".join(f"k_cells<{c},{tuning['waves_per_cell']},{mode}>" for c in caps)
     achieved = alg_bytes / K / (per_launch_ms.mean() / 1e3) / 1e9
-    traffic = traffic_from_profiles("k_cells", args.workload, alg_bytes / K)
+    traffic = traffic_from_profiles("k_cells", args.workload, alg_bytes / K, tuning)
     line = {
         "metric": METRIC,
         "value": value,

@@ -23,17 +23,24 @@ def test_launched_classes():
 def test_traffic_summary_is_consistent():
     path = os.path.join(bench.PROFILES, "k_cells_grid256_pmc.json")
     d = json.load(open(path))
-    for key in ("kernel_source_sha", "fetch_kib_per_dispatch", "write_kib_per_dispatch",
-                "fetch_scale", "write_scale", "commands"):
+    for key in ("kernel_source_sha", "shapes"):
         assert key in d
-    assert abs(d["fetch_kib_per_dispatch"] - d["fetch_kib_per_dispatch_raw"] * d["fetch_scale"]) < 1
-    # the scale factors come from a 1 GiB copy: expected KiB / counted KiB
-    cp = d["copy_probe"]
-    assert abs(d["fetch_scale"] - cp["bytes"] / 1024 / cp["fetch_kib_raw"]) < 1e-9
-    assert abs(d["write_scale"] - cp["bytes"] / 1024 / cp["write_kib_raw"]) < 1e-9
-    # the traffic is only used while the kernel source matches the summary
-    got = bench.traffic_from_profiles("k_cells", "grid256", 0)
-    if d["kernel_source_sha"] == bench.kernel_source_sha():
-        assert got == (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0
-    else:
-        assert got is None
+    for key, shape in d["shapes"].items():
+        # the scale factors come from a 1 GiB copy: expected KiB / counted KiB
+        cp = shape["copy_probe"]
+        assert abs(shape["fetch_scale"] - cp["bytes"] / 1024 / cp["fetch_kib_raw"]) < 1e-9
+        assert abs(shape["write_scale"] - cp["bytes"] / 1024 / cp["write_kib_raw"]) < 1e-9
+        mask, waves = key.split("/")
+        # per step: the sum over the step's kernels of (KiB per dispatch x dispatches per step)
+        f = sum(k["fetch_kib_per_dispatch_raw"] * k["per_step"] for k in shape["kernels"])
+        w = sum(k["write_kib_per_dispatch_raw"] * k["per_step"] for k in shape["kernels"])
+        assert abs(shape["fetch_kib_per_step"] - f * shape["fetch_scale"]) < 1
+        assert abs(shape["write_kib_per_step"] - w * shape["write_scale"]) < 1
+        tuning = {"wave_class_mask": int(mask, 16), "waves_per_cell": int(waves)}
+        got = bench.traffic_from_profiles("k_cells", "grid256", 0, tuning)
+        if d["kernel_source_sha"] == bench.kernel_source_sha():
+            assert got == (shape["fetch_kib_per_step"] + shape["write_kib_per_step"]) * 1024.0
+        else:
+            assert got is None
+    assert bench.traffic_from_profiles("k_cells", "grid256", 0, {"wave_class_mask": 0x1F,
+                                                                 "waves_per_cell": 8}) is None
