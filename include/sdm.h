@@ -30,7 +30,9 @@
  *     memory owned by the caller (e.g. torch tensors).  The library borrows
  *     the state arrays (xi, v, attrs, cell_off) and the workspace for the
  *     lifetime of the handle; it never allocates or frees device memory.
- *   - The library allocates only the host-side handle; sdm_free releases it.
+ *   - The library allocates only the host-side handle and, at the first step
+ *     of a simulation or batch, one more HIP stream (default priority) and two
+ *     events; sdm_free / sdm_batch_free release them.
  *   - Layout is structure-of-arrays: xi[n_slots] (int64), v[n_slots] (float64,
  *     m^3), attrs[n_attr][n_slots] (float64, extra extensive attributes summed
  *     on coalescence like volume), cell_off[n_cells + 1] (int64, slots of cell
@@ -43,7 +45,10 @@
  * word (sdm_status_word).
  *
  * Threading.  Step and moments calls only enqueue work on `stream` and return.
- * One handle must not be stepped on two streams at once.
+ * Part of a step may run on the library's second stream, which waits for
+ * `stream` (an event) and is joined back into it before the call returns, so
+ * work enqueued on `stream` afterwards sees the step complete.  One handle
+ * must not be stepped on two streams at once.
  */
 #ifndef SDM_H
 #define SDM_H
@@ -99,7 +104,9 @@ typedef struct {
   int32_t waves_per_cell;    /* 1, 2, 4 or 8: wavefronts in the workgroup of one cell */
   int32_t big_bucket_target; /* cells on the big-cell path: expected SDs per sort bucket,
                                 32..1024 */
-  int32_t lpt_order;         /* 1: dispatch cells by descending size */
+  int32_t lpt_order;         /* 1: dispatch cells by descending size (adaptive cells: at the
+                                first step; after it they go by the substeps they took in
+                                the step before, most first) */
   int32_t mid_max_slots;     /* cells of 513..mid_max_slots slots (<= 16384) get one workgroup
                                 each (mid-size kernel); larger ones take the multi-pass
                                 big-cell path; 0 sends every cell above 512 there */
