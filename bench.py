@@ -189,6 +189,37 @@ def batched_vs_separate(state, tuning, n_cells=256, steps=5):
             "separate_sd_steps_per_s": separate, "speedup": batched / separate}
 
 
+def fused_vs_single(state, tuning, steps=40):
+    """The same steps from the same state taken one call per step (one launch
+    per step and class, as timed for `value`) and in one call (the library
+    fuses up to 8 steps per launch, each cell kept in LDS across them);
+    milliseconds per step of both.  A separate figure, never the headline."""
+    import torch
+
+    from paper_2103_17238_amd import binding as B
+
+    out = {}
+    for name in ("single", "fused"):
+        sim = B.Sim(state)
+        t = B.sdm_get_tuning(sim.handle)
+        t.wave_class_mask, t.waves_per_cell = tuning["wave_class_mask"], tuning["waves_per_cell"]
+        B.sdm_set_tuning(sim.handle, t)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if name == "single":
+            for _ in range(steps):
+                sim.step(1)
+        else:
+            sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / steps
+        sim.close()
+    return {"steps": steps, "single_ms_per_step": out["single"],
+            "fused_ms_per_step": out["fused"], "speedup": out["single"] / out["fused"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +399,7 @@ def main():
     sim.close()
     if cell_grid and not args.no_batching_check:
         line["batching"] = batched_vs_separate(host_state, tuning)
+        line["fusion"] = fused_vs_single(host_state, tuning)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(host_state, args.cpu_cells, args.cpu_steps)
     else:

@@ -405,10 +405,12 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
       return SDM_EDEVICE;
     }
   }
-  for (int64_t k = 0; k < active; ++k) {
-    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->flip++, p->tuning.waves_per_cell,
-                         st, p->side) != hipSuccess)
+  for (int64_t k = 0; k < active;) {  // up to kFuseMax steps per launch
+    const int f = (int)std::min<int64_t>(sdm::kFuseMax, active - k);
+    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->flip++, f,
+                         p->tuning.waves_per_cell, st, p->side) != hipSuccess)
       return SDM_EDEVICE;
+    k += f;
   }
   p->counter += (uint32_t)n_steps;
   for (auto* s : p->members) {

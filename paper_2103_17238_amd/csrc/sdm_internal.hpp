@@ -18,6 +18,7 @@ constexpr int kBucketCap = 1024;  // big-cell bucket entries staged in LDS by on
 constexpr int kMinBucketTarget = 32;
 constexpr int kOrderBlock = 1024;  // tasks per block of the dispatch-order partition
 constexpr int kOrderGroups = 4;    // dispatch-order groups by substeps taken
+constexpr int kFuseMax = 8;        // steps of a multi-step call fused in one launch
 
 constexpr uint32_t kFlagSubstepCap = 1u;
 constexpr uint32_t kFlagGammaCap = 2u;
@@ -130,10 +131,13 @@ struct SideStream {
 };
 
 // launches (sdm_kernels.hip)
-// flip: count of steps launched on this plan since its tables were built
-// (selects which of the two adaptive task lists a step reads)
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int waves_per_cell,
-                       hipStream_t st, const SideStream& side);
+// Enqueues nsteps (1..kFuseMax) steps starting at launch step k_abs: the
+// workgroup-per-cell classes in one launch each (several steps fused), the
+// mid-size and big cells one step per launch.  flip: launches made on this
+// plan since its tables were built (selects which of the two adaptive task
+// lists is read).
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
+                       int waves_per_cell, hipStream_t st, const SideStream& side);
 hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
                           double* attr_sums, const double* edges, int n_bins, double* spectrum,
                           hipStream_t st);

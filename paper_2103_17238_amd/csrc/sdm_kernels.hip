@@ -165,12 +165,13 @@ __device__ __forceinline__ int wave_excl_scan(int x, int lane) {
 }
 
 __device__ __forceinline__ void add_stats(unsigned long long* stats, unsigned long long live,
-                                          unsigned long long coll, unsigned long long substeps) {
+                                          unsigned long long coll, unsigned long long substeps,
+                                          unsigned long long steps = 1) {
   unsigned long long* s = stats + (blockIdx.x % kStatSlots) * kStatFields;
   if (live) atomicAdd(s + 0, live);
   if (coll) atomicAdd(s + 1, coll);
   if (substeps) atomicAdd(s + 2, substeps);
-  atomicAdd(s + 3, 1ull);
+  if (steps) atomicAdd(s + 3, steps);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,13 +435,14 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
   team_sync<W>();
 }
 
-enum PassMode { kPassPlain = 0, kPassPmax = 1, kPassAdapt = 2 };
+enum PassMode { kPassPlain = 0, kPassPmax = 1, kPassAdapt = 2, kPassPlainLds = 3 };
 
 // Candidate pairs of one (sub)step; thread h takes sorted positions 4h..4h+3,
 // i.e. pairs 2h and 2h+1, which share one Philox call.  kPassPlain updates
-// global memory; kPassPmax stores the pre-products (max xi K) S and returns
-// this thread's largest p at q; kPassAdapt reads them back, clamps p to 1 if
-// asked and updates LDS.
+// global memory; kPassPlainLds computes p the same way and updates LDS (steps
+// fused in one launch); kPassPmax stores the pre-products (max xi K) S and
+// returns this thread's largest p at q; kPassAdapt reads them back, clamps p
+// to 1 if asked and updates LDS.
 template <int CAP, int W, int MODE>
 __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp, int n,
                                              int nlive, int tid, int c, uint32_t s, uint32_t u,
@@ -505,10 +507,12 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
           update_pair(dp->xi + o0, dp->v + o0, a, bb, xa, xb, va, vb, gamma, dp->attrs,
                       dp->n_slots, dp->n_attr, o0 + a, o0 + bb);
         } else {
-          xa = L.xs[a];
-          xb = L.xs[bb];
-          va = L.vs[a];
-          vb = L.vs[bb];
+          if (MODE == kPassAdapt) {
+            xa = L.xs[a];
+            xb = L.xs[bb];
+            va = L.vs[a];
+            vb = L.vs[bb];
+          }
           *ndead += update_pair(L.xs, L.vs, a, bb, xa, xb, va, vb, gamma, dp->attrs,
                                 dp->n_slots, dp->n_attr, o0 + a, o0 + bb);
           atomicOr(&L.dirty[a >> 5], 1u << (a & 31));
@@ -543,7 +547,7 @@ __device__ __forceinline__ void sink_clear_cell(const SimDesc* dp, int c, int n,
 template <int CAP, int W, bool ADAPT>
 __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ descs,
                                                   const CellTask* __restrict__ tasks,
-                                                  uint32_t k_abs,
+                                                  uint32_t k_abs, int nsteps,
                                                   uint32_t* __restrict__ order_flag) {
   constexpr int T = 64 * W;
   constexpr int IT = (CAP + T - 1) / T;
@@ -569,12 +573,15 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
   const int c = cur.cell;
   const SimDesc* dp = descs + cur.sim;
   const int64_t o0 = cur.xi - dp->xi;
-  const uint32_t s = k_abs + dp->step_delta;
-  if (s >= dp->step_limit) {  // uniform over the block
+  const uint32_t s0 = k_abs + dp->step_delta;
+  if (s0 >= dp->step_limit) {  // uniform over the block
     if (ADAPT && tid == 0) order_flag[blockIdx.x] = order_group(0);
     return;
   }
-  if (ADAPT)
+  // Several steps in one launch (nsteps > 1) keep the cell in LDS from step
+  // to step; each step is exactly the single step it replaces.
+  const bool in_lds = ADAPT || nsteps > 1;
+  if (in_lds)
     for (int k = tid; k < CAP / 32; k += T) L.dirty[k] = 0;
   int mylive = 0;
 #pragma unroll
@@ -589,53 +596,83 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
   const int nlive = team_sum<W>(L, mylive, lane, wv);  // also orders the LDS stores
 
   int ncoll = 0;
-  int nsub = 1;
-  if (!ADAPT) {
+  unsigned long long live_sum = 0, nsub = 0, steps_done = 0;
+  if (!in_lds) {  // one plain step: updates go straight to global memory
     if (nlive >= 2) {
-      team_sort<CAP, W>(L, n, nlive, tid, lane, wv, c, s, 0u, dp->seed_lo, dp->seed_hi);
-      team_pairs<CAP, W, kPassPlain>(L, dp, n, nlive, tid, c, s, 0u, dp->q, false, o0, &ncoll);
+      team_sort<CAP, W>(L, n, nlive, tid, lane, wv, c, s0, 0u, dp->seed_lo, dp->seed_hi);
+      team_pairs<CAP, W, kPassPlain>(L, dp, n, nlive, tid, c, s0, 0u, dp->q, false, o0,
+                                     &ncoll);
     } else {
       sink_clear_cell(dp, c, n, tid, T);
     }
+    live_sum = (unsigned long long)nlive;
+    nsub = 1;
+    steps_done = 1;
   } else {
-    // Per-cell substepping: the substep length keeps every p <= 1 (p is
-    // clamped to 1), so gamma <= 1.  After max_substeps substeps the rest of
-    // the step is done in one unclamped substep and SUBSTEP_CAP is raised.
-    const double dv = dp->dv;
-    double dt_left = dp->dt;
-    uint32_t u = 0;
-    const uint32_t umax = (uint32_t)dp->max_substeps;
-    int nl = nlive;  // live SDs: a substep only empties slots by multiplicity-1 splits
-    while (dt_left > 0.0) {
-      const bool capped = u >= umax;
-      if (capped && tid == 0) atomicOr(dp->status, kFlagSubstepCap);
-      if (nl < 2) {
-        if (capped) {
+    int nl = nlive;  // live SDs: a step only empties slots by multiplicity-1 splits
+    for (int t = 0; t < nsteps; ++t) {
+      const uint32_t s = s0 + (uint32_t)t;
+      if (s >= dp->step_limit) break;  // uniform over the block
+      live_sum += (unsigned long long)nl;
+      steps_done += 1;
+      if (!ADAPT) {
+        if (nl >= 2) {
+          team_sort<CAP, W>(L, n, nl, tid, lane, wv, c, s, 0u, dp->seed_lo, dp->seed_hi);
+          int ndead = 0;
+          team_pairs<CAP, W, kPassPlainLds>(L, dp, n, nl, tid, c, s, 0u, dp->q, false, o0,
+                                            &ncoll, &ndead);
+          nl -= team_sum<W>(L, ndead, lane, wv);
+        } else {
           sink_clear_cell(dp, c, n, tid, T);
-          u += 1;
         }
-        break;
+        nsub += 1;
+      } else {
+        // Per-cell substepping: the substep length keeps every p <= 1 (p is
+        // clamped to 1), so gamma <= 1.  After max_substeps substeps the rest
+        // of the step is done in one unclamped substep and SUBSTEP_CAP is
+        // raised.
+        const double dv = dp->dv;
+        double dt_left = dp->dt;
+        uint32_t u = 0;
+        const uint32_t umax = (uint32_t)dp->max_substeps;
+        while (dt_left > 0.0) {
+          const bool capped = u >= umax;
+          if (capped && tid == 0) atomicOr(dp->status, kFlagSubstepCap);
+          if (nl < 2) {
+            if (capped) {
+              sink_clear_cell(dp, c, n, tid, T);
+              u += 1;
+            }
+            break;
+          }
+          team_sort<CAP, W>(L, n, nl, tid, lane, wv, c, s, u, dp->seed_lo, dp->seed_hi);
+          double pmax = team_pairs<CAP, W, kPassPmax>(L, dp, n, nl, tid, c, s, u,
+                                                      dt_left / dv, false, o0, &ncoll);
+          pmax = team_max<W>(L, pmax, lane, wv);
+          const double dt_sub = (capped || pmax <= 1.0) ? dt_left : dt_left / pmax;
+          int ndead = 0;
+          team_pairs<CAP, W, kPassAdapt>(L, dp, n, nl, tid, c, s, u, dt_sub / dv, !capped, o0,
+                                         &ncoll, &ndead);
+          nl -= team_sum<W>(L, ndead, lane, wv);
+          // the next substep's attribute loads come from this same workgroup:
+          // one CU, one vector L1, so ordering the stores before them is all
+          // it takes
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          team_sync<W>();
+          dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
+          u += 1;
+          if (capped) break;
+        }
+        if (u == 0) sink_clear_cell(dp, c, n, tid, T);
+        nsub += u;
       }
-      team_sort<CAP, W>(L, n, nl, tid, lane, wv, c, s, u, dp->seed_lo, dp->seed_hi);
-      double pmax = team_pairs<CAP, W, kPassPmax>(L, dp, n, nl, tid, c, s, u, dt_left / dv,
-                                                  false, o0, &ncoll);
-      pmax = team_max<W>(L, pmax, lane, wv);
-      const double dt_sub = (capped || pmax <= 1.0) ? dt_left : dt_left / pmax;
-      int ndead = 0;
-      team_pairs<CAP, W, kPassAdapt>(L, dp, n, nl, tid, c, s, u, dt_sub / dv, !capped, o0,
-                                     &ncoll, &ndead);
-      nl -= team_sum<W>(L, ndead, lane, wv);
-      // the next substep's attribute loads come from this same workgroup: one
-      // CU, one vector L1, so ordering the stores before them is all it takes
+      // this step's attribute updates before the next step's
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       team_sync<W>();
-      dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
-      u += 1;
-      if (capped) break;
     }
-    if (u == 0) sink_clear_cell(dp, c, n, tid, T);
-    nsub = (int)u;
-    if (tid == 0) order_flag[blockIdx.x] = order_group(u);  // next step's dispatch order
+    if (ADAPT && tid == 0)  // next launch's dispatch order: substeps per step
+      order_flag[blockIdx.x] =
+          order_group((uint32_t)((nsub + steps_done - 1) / (steps_done ? steps_done : 1)));
     team_sync<W>();
     // write back the slots that changed
     for (int j = tid; j < n; j += T) {
@@ -646,8 +683,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
     }
   }
   ncoll = team_sum<W>(L, ncoll, lane, wv);
-  if (tid == 0) add_stats(dp->stats, (unsigned long long)nlive, (unsigned long long)ncoll,
-                          (unsigned long long)nsub);
+  if (tid == 0) add_stats(dp->stats, live_sum, (unsigned long long)ncoll, nsub, steps_done);
 }
 
 // ---------------------------------------------------------------------------
@@ -1368,19 +1404,19 @@ void set_lds_limits() {
 }
 
 template <int CAP, int W>
-static void launch_class_w(const PlanDev& p, int cls, uint32_t k_abs, uint32_t flip,
+static void launch_class_w(const PlanDev& p, int cls, uint32_t k_abs, uint32_t flip, int nsteps,
                            hipStream_t st) {
   const int np = p.n_plain[cls], na = p.n_wave[cls] - p.n_plain[cls];
   if (np > 0)
     hipLaunchKernelGGL((k_cells<CAP, W, false>), dim3(np), dim3(64 * W), 0, st, p.desc,
-                       p.wave_tasks[cls], k_abs, nullptr);
+                       p.wave_tasks[cls], k_abs, nsteps, nullptr);
   if (na > 0) {
     // the adaptive list of this step, and the one the next step will use
     const uint32_t par = flip & 1u;
     CellTask* cur = par ? p.wave_alt[cls] : p.wave_tasks[cls] + np;
     CellTask* nxt = par ? p.wave_tasks[cls] + np : p.wave_alt[cls];
     hipLaunchKernelGGL((k_cells<CAP, W, true>), dim3(na), dim3(64 * W), 0, st, p.desc, cur,
-                       k_abs, p.order_flag[cls]);
+                       k_abs, nsteps, p.order_flag[cls]);
     const int nb = (na + kOrderBlock - 1) / kOrderBlock;
     hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(kOrderBlock), 0, st, p.order_flag[cls],
                        p.order_cnt[cls], na);
@@ -1390,13 +1426,13 @@ static void launch_class_w(const PlanDev& p, int cls, uint32_t k_abs, uint32_t f
 }
 
 template <int CAP>
-static void launch_class(const PlanDev& p, int cls, uint32_t k_abs, uint32_t flip, int w,
-                         hipStream_t st) {
+static void launch_class(const PlanDev& p, int cls, uint32_t k_abs, uint32_t flip, int nsteps,
+                         int w, hipStream_t st) {
   switch (w) {
-    case 1: launch_class_w<CAP, 1>(p, cls, k_abs, flip, st); break;
-    case 2: launch_class_w<CAP, 2>(p, cls, k_abs, flip, st); break;
-    case 4: launch_class_w<CAP, 4>(p, cls, k_abs, flip, st); break;
-    default: launch_class_w<CAP, 8>(p, cls, k_abs, flip, st); break;
+    case 1: launch_class_w<CAP, 1>(p, cls, k_abs, flip, nsteps, st); break;
+    case 2: launch_class_w<CAP, 2>(p, cls, k_abs, flip, nsteps, st); break;
+    case 4: launch_class_w<CAP, 4>(p, cls, k_abs, flip, nsteps, st); break;
+    default: launch_class_w<CAP, 8>(p, cls, k_abs, flip, nsteps, st); break;
   }
 }
 
@@ -1422,8 +1458,9 @@ static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st
                        p.mid_tasks[cls] + np, k_abs);
 }
 
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int waves_per_cell,
-                       hipStream_t st, const SideStream& side) {
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
+                       int waves_per_cell, hipStream_t st, const SideStream& side) {
+  const uint32_t k_abs0 = k_abs;
   // Two independent groups of launches run on two streams and fill each
   // other's tails: the cells of up to 256 slots and the mid-size cells on a
   // second stream, the 384- and 512-slot classes and the big-cell chain on
@@ -1439,16 +1476,19 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int wave
       return hipErrorUnknown;
     st2 = side.stream;
   }
-  launch_class<256>(p, 2, k_abs, flip, waves_per_cell, st2);
-  launch_class<128>(p, 1, k_abs, flip, waves_per_cell, st2);
-  launch_class<64>(p, 0, k_abs, flip, waves_per_cell, st2);
-  launch_mid<16384>(p, 3, k_abs, st2);
-  launch_mid<8192>(p, 2, k_abs, st2);
-  launch_mid<4096>(p, 1, k_abs, st2);
-  launch_mid<2048>(p, 0, k_abs, st2);
-  launch_class<512>(p, 4, k_abs, flip, waves_per_cell, st);
-  launch_class<384>(p, 3, k_abs, flip, waves_per_cell, st);
-  if (p.n_big > 0) {
+  launch_class<256>(p, 2, k_abs, flip, nsteps, waves_per_cell, st2);
+  launch_class<128>(p, 1, k_abs, flip, nsteps, waves_per_cell, st2);
+  launch_class<64>(p, 0, k_abs, flip, nsteps, waves_per_cell, st2);
+  for (int t = 0; t < nsteps; ++t) {  // mid-size cells: one launch per step
+    launch_mid<16384>(p, 3, k_abs + t, st2);
+    launch_mid<8192>(p, 2, k_abs + t, st2);
+    launch_mid<4096>(p, 1, k_abs + t, st2);
+    launch_mid<2048>(p, 0, k_abs + t, st2);
+  }
+  launch_class<512>(p, 4, k_abs, flip, nsteps, waves_per_cell, st);
+  launch_class<384>(p, 3, k_abs, flip, nsteps, waves_per_cell, st);
+  for (int t = 0; t < nsteps && p.n_big > 0; ++t) {  // big cells: five launches per step
+    const uint32_t k_abs = k_abs0 + t;
     hipLaunchKernelGGL(k_big_count, dim3(p.n_chunks), dim3(256), 0, st, p.desc, p.big, p.chunks,
                        p.bucket_cnt, p.task_live, k_abs);
     hipLaunchKernelGGL(k_big_scan, dim3(p.n_big), dim3(256), 0, st, p.desc, p.big, p.bucket_cnt,

@@ -391,6 +391,45 @@ def test_batch_equals_separate(B, orc):
         r.close()
 
 
+@pytest.mark.parametrize("case", ["plain-golovin", "plain-geometric", "adaptive", "limit"])
+def test_fused_steps_equal_single_steps(B, orc, case):
+    """A multi-step call fuses up to 8 steps per launch with each cell kept
+    in LDS; the result, the pair log of the last step and the statistics
+    equal those of the same steps taken one call at a time (and, for the
+    Golovin case, the oracle's)."""
+    if case == "plain-golovin":
+        st = I.random_cells(40, 500, n_attr=2, rng_seed=81, p_boost=30.0)
+    elif case == "plain-geometric":
+        st = I.grid(8, 8, 200, max_sd=380, n_attr=3, kernel=I.GEOMETRIC, seed=4)
+    else:
+        st = I.grid(8, 8, 200, max_sd=380, n_attr=3, kernel=I.GEOMETRIC, drizzle=True,
+                    adaptive=True, seed=6)
+    steps = 19  # fused launches of 8, 8 and 3 steps
+    one = GpuRun(B, st, sink=True)
+    many = GpuRun(B, st, sink=True)
+    if case == "limit":  # the limit falls inside the second fused launch
+        B.sdm_set_step_limit(one.sim.handle, 11)
+        B.sdm_set_step_limit(many.sim.handle, 11)
+    say(f"fused steps: {case}")
+    for _ in range(steps):
+        one.step(1)
+    many.step(steps)
+    for x, y in zip(one.state(), many.state()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(one.log(), many.log())
+    assert B.sdm_stats(one.sim.handle) == B.sdm_stats(many.sim.handle)
+    assert B.sdm_get_step(one.sim.handle) == B.sdm_get_step(many.sim.handle)
+    if case == "plain-golovin":
+        o = st.copy()
+        cfg = ocfg(orc, o)
+        for s_ in range(steps):
+            orc.step(cfg, o.xi, o.v, o.attrs, o.cell_off, s_)
+        xi, v, at = many.state()
+        assert np.array_equal(xi, o.xi) and np.array_equal(v, o.v) and np.array_equal(at, o.attrs)
+    one.sim.close()
+    many.sim.close()
+
+
 def test_invalid_inputs(B):
     import torch
 
