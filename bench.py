@@ -17,6 +17,12 @@ SD through one outer step).  Algorithmic bytes per step: 16 per live SD
 (read xi and v), 8 per dead slot (read xi), (32 + 32 A) per colliding pair,
 8 per cell (offsets).
 
+The step timed for `value` is one call per step (one launch per class).
+Separate figures in the same line: `batching` (a sample of cells as one
+simulation against the same cells as separate simulations) and `fusion` (the
+same steps in one call, which the library runs up to 8 steps per launch with
+each cell kept in LDS).
+
 Prints ONE JSON line.  --gpus above 1 is refused: the benchmark measures one
 GPU.
 """
@@ -303,7 +309,8 @@ def main():
                 probe.step(2)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                probe.step(4)
+                for _ in range(4):  # one call per step, as timed below
+                    probe.step(1)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / 4
