@@ -282,3 +282,54 @@ def random_cells(n_cells: int, max_sd: int, n_attr: int = 0, kernel: int = GOLOV
         np.zeros((0, n))
     return State(xi, v, attrs, cell_off, dt=1.0, dv=dv, kernel=kernel, b=1500.0 * p_boost,
                  seed=rng_seed, meta={"workload": "random_cells"})
+
+
+# ---------------------------------------------------------------------------
+# Kinematic 2D set-up for displacement: droplet positions and a prescribed
+# single-eddy flow given as face Courant numbers (inputs only: the
+# displacement arithmetic is not here)
+# ---------------------------------------------------------------------------
+
+def positions(n: int, seed: int = 4) -> np.ndarray:
+    """Positions of n droplets inside their cells: (2, n) fractions in [0, 1),
+    uniform, from numpy.random.default_rng(seed)."""
+    return np.random.default_rng(seed).random((2, n))
+
+
+def single_eddy_courant(nx: int, nz: int, dt: float = 1.0, dx: float = 20.0, dz: float = 20.0,
+                        w_max: float = 0.6):
+    """Face Courant numbers of a non-divergent single-eddy flow over an
+    nx x nz periodic-in-x domain (updraft in one half, downdraft in the other,
+    no flow through the bottom and top), from the stream function
+    psi(x, z) = -(w_max X / (2 pi)) sin(pi z / Z) cos(2 pi x / X) sampled at
+    the cell corners; u = -dpsi/dz, w = dpsi/dx as corner differences, so the
+    discrete divergence of every cell is zero up to rounding.
+    Returns (cx (nx + 1, nz), cz (nx, nz + 1)).  Defaults: 20 m cells,
+    w_max 0.6 m/s, dt 1 s (the drizzling stratocumulus set-up the paper's
+    kinematic 2D example follows)."""
+    X, Z = nx * dx, nz * dz
+    x = np.arange(nx + 1)[:, None] * dx
+    z = np.arange(nz + 1)[None, :] * dz
+    psi = -(w_max * X / (2 * np.pi)) * np.sin(np.pi * z / Z) * np.cos(2 * np.pi * x / X)
+    psi[:, 0] = 0.0
+    psi[:, nz] = 0.0
+    psi[nx, :] = psi[0, :]
+    cx = -(psi[:, 1:] - psi[:, :-1]) * dt / (dx * dz)
+    cz = (psi[1:, :] - psi[:-1, :]) * dt / (dx * dz)
+    return np.ascontiguousarray(cx), np.ascontiguousarray(cz)
+
+
+def uniform_courant(nx: int, nz: int, cx: float, cz: float):
+    """Face Courant numbers of a uniform flow."""
+    return np.full((nx + 1, nz), float(cx)), np.full((nx, nz + 1), float(cz))
+
+
+def random_courant(nx: int, nz: int, amp: float = 0.9, seed: int = 5):
+    """Face Courant numbers drawn uniformly from (-amp, amp) (not a physical
+    flow: exercises every shift direction and the periodic wrap)."""
+    rng = np.random.default_rng(seed)
+    cx = rng.uniform(-amp, amp, size=(nx + 1, nz))
+    cz = rng.uniform(-amp, amp, size=(nx, nz + 1))
+    cx[nx, :] = cx[0, :]
+    cz[:, nz] = cz[:, 0]
+    return cx, cz
