@@ -79,6 +79,7 @@ typedef enum { SDM_GOLOVIN = 0, SDM_GEOMETRIC = 1 } sdm_kernel_kind;
 #define SDM_FLAG_GAMMA_CAP 2u       /* some p >= 2^62: gamma capped at 2^62 */
 #define SDM_FLAG_BUCKET_OVERFLOW 4u /* big-cell sort used its slow path (still exact) */
 #define SDM_FLAG_INVALID_STATE 8u   /* validation found xi < 0, xi >= 2^53 or a bad volume */
+#define SDM_FLAG_COURANT 16u        /* displacement: some |d| >= 1 cell or a position outside [0, 1) */
 
 typedef struct {
   int64_t n_slots;        /* SD slots (live and dead), >= 0 */
@@ -204,6 +205,72 @@ void sdm_batch_free(sdm_batch* b);
 
 void sdm_free(sdm_sim* s);
 const char* sdm_strerror(sdm_status st);
+
+/*
+ * Re-point a simulation at new state arrays of the same n_slots and n_cells
+ * (for instance the output of sdm_displace, whose cell sizes differ) and
+ * re-plan its launches.  The step counter, tuning, statistics and status are
+ * kept.  Copies cell_off to the host (synchronises `stream`) and validates it
+ * like sdm_init; SDM_ENOMEM if the new layout needs more workspace than the
+ * handle was given (size it with sdm_workspace_bytes(cfg, NULL) to allow any
+ * layout).  A batch containing s must be re-created afterwards.
+ */
+sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const int64_t* cell_off,
+                      void* stream);
+
+/*
+ * Displacement and re-segmentation.  The paper lists particle displacement
+ * among the dynamics beside coalescence ("API in brief") and couples the
+ * particles to a prescribed single-eddy flow in its kinematic 2D example
+ * ("Kinematic (prescribed-flow) examples") without giving a scheme; this is
+ * one explicit first-order step:
+ *   - cells c = ix * nz + iz of an nx x nz domain, periodic in x and z,
+ *     nx, nz >= 3;
+ *   - pos[2][n_slots] (float64): each droplet's position inside its cell as
+ *     fractions wx = pos[0][j], wz = pos[1][j] in [0, 1);
+ *   - Courant numbers on cell faces: courant_x[(nx + 1) * nz], entry
+ *     ix * nz + iz on the face between cells ix - 1 and ix of row iz;
+ *     courant_z[nx * (nz + 1)], entry ix * (nz + 1) + iz on the face between
+ *     cells iz - 1 and iz of column ix;
+ *   - per axis d = (1 - w) c_low + w c_high (two products and a sum), w' = w + d,
+ *     the cell moves by floor(w') (wrapped), the new fraction is w' - floor(w')
+ *     (one that rounds to 1 becomes 0 in the next cell up);
+ *   - |d| < 1 is required: a droplet with |d| >= 1, or whose fraction is not
+ *     in [0, 1), raises SDM_FLAG_COURANT in *status (its move is clamped to one
+ *     cell per axis; the result is defined but not meaningful);
+ *   - the output state holds every slot (dead ones too) ordered by new cell;
+ *     inside a new cell the slots keep their old relative order (old cell,
+ *     then old slot).  cell_off_out is the new layout.
+ * All pointers are device memory owned by the caller; outputs must not
+ * overlap inputs.  An input cell_off that is not a valid layout of n_slots
+ * raises SDM_FLAG_INVALID_STATE and leaves the outputs unwritten.  Enqueue
+ * only (six small kernels, no allocation, no synchronisation).
+ */
+typedef struct {
+  int32_t nx, nz;          /* cells per axis, >= 3 each */
+  int32_t n_attr;          /* extra attributes, 0..16 */
+  int32_t reserved;        /* must be 0 */
+  int64_t n_slots;         /* 0 .. 2^32 - 1 */
+  const double* courant_x; /* [(nx + 1) * nz] */
+  const double* courant_z; /* [nx * (nz + 1)] */
+  const int64_t* xi;       /* input state, layout as in sdm_init */
+  const double* v;
+  const double* attrs; /* [n_attr][n_slots] */
+  const double* pos;   /* [2][n_slots] */
+  const int64_t* cell_off;
+  int64_t* xi_out; /* output state, same shapes */
+  double* v_out;
+  double* attrs_out;
+  double* pos_out;
+  int64_t* cell_off_out;
+  uint32_t* status; /* device word; SDM_FLAG_COURANT / SDM_FLAG_INVALID_STATE or-ed in */
+} sdm_displace_args;
+
+/* Workspace bytes of sdm_displace for an nx x nz domain (0 if invalid). */
+size_t sdm_displace_workspace_bytes(int32_t nx, int32_t nz);
+/* workspace: device, 256-byte aligned, >= sdm_displace_workspace_bytes. */
+sdm_status sdm_displace(const sdm_displace_args* args, void* workspace, size_t workspace_bytes,
+                        void* stream);
 
 /*
  * Test hook for the generator: out[4 i + w] = word w of Philox4x32-10 with

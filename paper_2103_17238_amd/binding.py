@@ -21,7 +21,7 @@ _lib = C.CDLL(_LIB_PATH)
 SDM_OK, SDM_EINVAL, SDM_ENOMEM, SDM_EDEVICE, SDM_ESTATE, SDM_EAGAIN = 0, -1, -2, -3, -4, -5
 SDM_GOLOVIN, SDM_GEOMETRIC = 0, 1
 SDM_FLAG_SUBSTEP_CAP, SDM_FLAG_GAMMA_CAP = 1, 2
-SDM_FLAG_BUCKET_OVERFLOW, SDM_FLAG_INVALID_STATE = 4, 8
+SDM_FLAG_BUCKET_OVERFLOW, SDM_FLAG_INVALID_STATE, SDM_FLAG_COURANT = 4, 8, 16
 
 EXPORTED = [
     "sdm_workspace_bytes", "sdm_init", "sdm_coalescence_step", "sdm_moments", "sdm_status_word",
@@ -29,6 +29,7 @@ EXPORTED = [
     "sdm_debug_gamma_sink", "sdm_get_tuning", "sdm_set_tuning", "sdm_autotune_scratch_bytes",
     "sdm_autotune", "sdm_batch_workspace_bytes", "sdm_batch_create", "sdm_batch_step",
     "sdm_batch_free", "sdm_free", "sdm_strerror", "sdm_philox_fill", "sdm_kernel_values",
+    "sdm_rebind", "sdm_displace_workspace_bytes", "sdm_displace",
 ]
 
 
@@ -97,6 +98,34 @@ _sig("sdm_strerror", C.c_char_p, _S)
 _sig("sdm_philox_fill", _S, _P, C.c_int64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
      C.c_uint64, _P)
 _sig("sdm_kernel_values", _S, C.c_int32, C.c_double, _P, _P, C.c_int64, _P, _P)
+
+
+class sdm_displace_args(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32),
+        ("nz", C.c_int32),
+        ("n_attr", C.c_int32),
+        ("reserved", C.c_int32),
+        ("n_slots", C.c_int64),
+        ("courant_x", _P),
+        ("courant_z", _P),
+        ("xi", _P),
+        ("v", _P),
+        ("attrs", _P),
+        ("pos", _P),
+        ("cell_off", _P),
+        ("xi_out", _P),
+        ("v_out", _P),
+        ("attrs_out", _P),
+        ("pos_out", _P),
+        ("cell_off_out", _P),
+        ("status", _P),
+    ]
+
+
+_sig("sdm_rebind", _S, _H, _P, _P, _P, _P, _P)
+_sig("sdm_displace_workspace_bytes", C.c_size_t, C.c_int32, C.c_int32)
+_sig("sdm_displace", _S, C.POINTER(sdm_displace_args), _P, C.c_size_t, _P)
 
 
 class SdmError(RuntimeError):
@@ -252,6 +281,26 @@ def sdm_free(h):
     _lib.sdm_free(h)
 
 
+def sdm_rebind(h, xi, v, attrs, cell_off, stream=None):
+    _check("sdm_rebind", _lib.sdm_rebind(h, _ptr(xi), _ptr(v), _ptr(attrs), _ptr(cell_off),
+                                         _stream(stream)))
+
+
+def sdm_displace_workspace_bytes(nx: int, nz: int) -> int:
+    return int(_lib.sdm_displace_workspace_bytes(int(nx), int(nz)))
+
+
+def sdm_displace(nx, nz, courant_x, courant_z, xi, v, attrs, pos, cell_off, xi_out, v_out,
+                 attrs_out, pos_out, cell_off_out, status, workspace, stream=None):
+    a = sdm_displace_args(int(nx), int(nz), int(attrs.shape[0]) if attrs is not None else 0, 0,
+                          int(xi.numel()), _ptr(courant_x), _ptr(courant_z), _ptr(xi), _ptr(v),
+                          _ptr(attrs), _ptr(pos), _ptr(cell_off), _ptr(xi_out), _ptr(v_out),
+                          _ptr(attrs_out), _ptr(pos_out), _ptr(cell_off_out), _ptr(status))
+    _check("sdm_displace", _lib.sdm_displace(C.byref(a), _ptr(workspace),
+                                             workspace.numel() * workspace.element_size(),
+                                             _stream(stream)))
+
+
 def sdm_strerror(st: int) -> str:
     return _lib.sdm_strerror(st).decode()
 
@@ -282,7 +331,7 @@ def workspace_tensor(nbytes, device="cuda"):
 class Sim:
     """One simulation: owns its device tensors and workspace, borrows nothing."""
 
-    def __init__(self, state, device="cuda", stream=None, max_substeps=0):
+    def __init__(self, state, device="cuda", stream=None, max_substeps=0, any_layout=False):
         import torch
 
         self.device = device
@@ -293,7 +342,9 @@ class Sim:
         self.attrs = (torch.from_numpy(np.ascontiguousarray(state.attrs)).to(device)
                       if state.n_attr else None)
         self.cell_off = torch.from_numpy(state.cell_off).to(device)
-        self.ws = workspace_tensor(sdm_workspace_bytes(self.cfg, state.cell_off), device)
+        # any_layout: workspace for every cell layout (sdm_rebind after displacement)
+        self.ws = workspace_tensor(
+            sdm_workspace_bytes(self.cfg, None if any_layout else state.cell_off), device)
         self.handle = sdm_init(self.cfg, self.xi, self.v, self.attrs, self.cell_off, self.ws,
                                stream)
 
@@ -337,3 +388,52 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+class Kinematic2D:
+    """Displacement of a Sim's droplets in a prescribed 2D flow (nx x nz cells,
+    c = ix * nz + iz): holds the face Courant numbers, the droplet positions
+    and a second set of state buffers; each step displaces and re-segments
+    into the other buffers and re-points the Sim at them (sdm_rebind).  The
+    Sim must have been made with any_layout=True."""
+
+    def __init__(self, sim: Sim, nx, nz, courant_x, courant_z, pos, stream=None):
+        import torch
+
+        dev = sim.device
+        self.sim, self.nx, self.nz = sim, int(nx), int(nz)
+        self.cx = torch.as_tensor(np.ascontiguousarray(courant_x, dtype=np.float64), device=dev)
+        self.cz = torch.as_tensor(np.ascontiguousarray(courant_z, dtype=np.float64), device=dev)
+        self.pos = torch.as_tensor(np.ascontiguousarray(pos, dtype=np.float64), device=dev)
+        self.other = (torch.empty_like(sim.xi), torch.empty_like(sim.v),
+                      torch.empty_like(sim.attrs) if sim.attrs is not None else None,
+                      torch.empty_like(self.pos), torch.empty_like(sim.cell_off))
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        nb = sdm_displace_workspace_bytes(nx, nz)
+        if nb == 0:
+            raise ValueError("displacement needs nx, nz >= 3")
+        self.ws = workspace_tensor(nb, dev)
+
+    def displace(self, stream=None):
+        """One displacement + re-segmentation (enqueue only); swaps buffers."""
+        s = self.sim
+        xo, vo, ao, po, oo = self.other
+        sdm_displace(self.nx, self.nz, self.cx, self.cz, s.xi, s.v, s.attrs, self.pos, s.cell_off,
+                     xo, vo, ao, po, oo, self.status, self.ws, stream)
+        self.other = (s.xi, s.v, s.attrs, self.pos, s.cell_off)
+        s.xi, s.v, s.attrs, self.pos, s.cell_off = xo, vo, ao, po, oo
+
+    def rebind(self, stream=None):
+        """Re-plan the Sim's coalescence launches for the current layout."""
+        s = self.sim
+        sdm_rebind(s.handle, s.xi, s.v, s.attrs, s.cell_off, stream)
+
+    def step(self, stream=None):
+        self.displace(stream)
+        self.rebind(stream)
+
+    def flags(self):
+        import torch
+
+        torch.cuda.synchronize()
+        return int(self.status.item()) & 0xFFFFFFFF

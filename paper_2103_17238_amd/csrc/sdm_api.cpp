@@ -683,6 +683,42 @@ sdm_status sdm_set_tuning(sdm_sim* s, const sdm_tuning* t, void* stream) {
   return plan_setup(s->plan, reinterpret_cast<hipStream_t>(stream));
 }
 
+sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const int64_t* cell_off,
+                      void* stream) {
+  if (!s || !cell_off) return SDM_EINVAL;
+  const sdm_config& cfg = s->cfg;
+  if (cfg.n_slots > 0 && (!xi || !v)) return SDM_EINVAL;
+  if (cfg.n_attr > 0 && cfg.n_slots > 0 && !attrs) return SDM_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<int64_t> off((size_t)cfg.n_cells + 1);
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(off.data(), cell_off, sizeof(int64_t) * off.size(), hipMemcpyDeviceToHost) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return SDM_EDEVICE;
+  }
+  if (!offsets_ok(&cfg, off.data())) return SDM_EINVAL;
+  if (cfg.adaptive)
+    for (int c = 0; c < cfg.n_cells; ++c)
+      if (off[c + 1] - off[c] > sdm::kMidCapMax) return SDM_EINVAL;
+  if (s->ws_bytes < sim_region_bytes(cfg.n_cells) + plan_bytes_for(&cfg, off.data()))
+    return SDM_ENOMEM;
+  std::vector<int64_t> pb((size_t)cfg.n_cells + 1, 0);
+  for (int c = 0; c < cfg.n_cells; ++c) pb[c + 1] = pb[c] + (off[c + 1] - off[c]) / 2;
+  if (hipMemcpy(s->d_pair_base, pb.data(), sizeof(int64_t) * pb.size(), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return SDM_EDEVICE;
+  }
+  s->xi = xi;
+  s->v = v;
+  s->attrs = cfg.n_attr > 0 ? attrs : nullptr;
+  s->cell_off = cell_off;
+  s->off.swap(off);
+  s->plan->counter = s->step;
+  return plan_setup(s->plan, st);
+}
+
 void sdm_free(sdm_sim* s) {
   if (!s) return;
   delete s->plan;

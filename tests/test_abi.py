@@ -43,3 +43,39 @@ def test_host_side_sizes_and_errors():
     assert B.sdm_workspace_bytes(B.make_config(10, 2, dt_s=-1.0)) == 0
     assert B.sdm_workspace_bytes(cfg, [0, 100, 50, 700, 1000]) == 0  # offsets not monotone
     assert B.sdm_strerror(B.SDM_ENOMEM) == "workspace too small"
+
+
+def test_displace_argument_checks():
+    """Argument errors of sdm_displace are caught on the host before any HIP
+    call (fake device addresses are never dereferenced)."""
+    import ctypes as C
+
+    from paper_2103_17238_amd import binding as B
+
+    assert B.sdm_displace_workspace_bytes(2, 5) == 0
+    assert B.sdm_displace_workspace_bytes(3, 3) > 0
+    lib = C.CDLL(B.library_path())
+    f = lib.sdm_displace
+    f.restype = C.c_int
+    f.argtypes = [C.POINTER(B.sdm_displace_args), C.c_void_p, C.c_size_t, C.c_void_p]
+
+    def args(nx=4, nz=4, n=100, A=1, **kw):
+        base = 1 << 40
+        a = B.sdm_displace_args(nx, nz, A, 0, n)
+        names = ["courant_x", "courant_z", "xi", "v", "attrs", "pos", "cell_off", "xi_out",
+                 "v_out", "attrs_out", "pos_out", "cell_off_out", "status"]
+        for k, nm in enumerate(names):
+            setattr(a, nm, base + (k << 24))
+        for k, val in kw.items():
+            setattr(a, k, val)
+        return a
+
+    ws = 1 << 45
+    good = args()
+    assert f(C.byref(args(nx=2)), ws, 1 << 30, None) == B.SDM_EINVAL
+    assert f(C.byref(args(A=17)), ws, 1 << 30, None) == B.SDM_EINVAL
+    assert f(C.byref(args(reserved=1)), ws, 1 << 30, None) == B.SDM_EINVAL
+    assert f(C.byref(args(xi=None)), ws, 1 << 30, None) == B.SDM_EINVAL
+    assert f(C.byref(args(xi_out=good.xi + 8)), ws, 1 << 30, None) == B.SDM_EINVAL  # overlap
+    assert f(C.byref(good), ws + 8, 1 << 30, None) == B.SDM_EINVAL  # misaligned workspace
+    assert f(C.byref(good), ws, 16, None) == B.SDM_ENOMEM
