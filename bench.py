@@ -232,7 +232,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="grid256",
-                    choices=["grid256", "grid64", "golovin", "geometric", "serving"])
+                    choices=["grid256", "grid64", "golovin", "geometric", "serving", "displace"])
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--mask", type=lambda x: int(x, 0), default=None,
                     help="fixed class mask (skips the autotuner; e.g. 0x18)")
@@ -275,6 +275,8 @@ def main():
         del src, dst
     if args.workload == "serving":
         return serve_bench(args)
+    if args.workload == "displace":
+        return displace_bench(args)
     state, workload = make_state(args.workload)
     host_state = state.copy()
     sim = B.Sim(state)
@@ -409,6 +411,95 @@ def main():
         line["fusion"] = fused_vs_single(host_state, tuning)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(host_state, args.cpu_cells, args.cpu_steps)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+def displace_bench(args):
+    """Displacement + re-segmentation of the 256 x 256 grid (16.8 M slots, 6
+    attributes) in the single-eddy flow (20 m cells, w_max 0.6 m/s, dt 1 s):
+    one step = one sdm_displace call (six kernels) from one set of state
+    buffers into the other.  Algorithmic bytes per step: one read and one
+    write of every slot's xi, v, attributes and position ((32 + 8 A) x 2 =
+    160 B per slot), the cell offsets (16 B per cell) and the face Courant
+    numbers."""
+    import numpy as np
+    import torch
+
+    from paper_2103_17238_amd import binding as B
+    from paper_2103_17238_amd import inputs as I
+
+    st = I.grid_256x256()
+    nx = nz = 256
+    cx, cz = I.single_eddy_courant(nx, nz)
+    pos = I.positions(st.n_slots)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    bufs = [[dev(st.xi), dev(st.v), dev(st.attrs), dev(pos), dev(st.cell_off)]]
+    bufs.append([torch.empty_like(t) for t in bufs[0]])
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = B.workspace_tensor(B.sdm_displace_workspace_bytes(nx, nz))
+    dcx, dcz = dev(cx), dev(cz)
+    stream = torch.cuda.current_stream()
+    k = [0]
+
+    def one():
+        a, b = bufs[k[0] & 1], bufs[(k[0] + 1) & 1]
+        B.sdm_displace(nx, nz, dcx, dcz, *a, *b, status, ws, stream)
+        k[0] += 1
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    w0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        one()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    per = [e0.elapsed_time(e1) / 1e3 for e0, e1 in evs]
+    total_s = evs[0][0].elapsed_time(evs[-1][1]) / 1e3
+    ms = total_s / args.steps * 1e3
+    n, A, C = st.n_slots, st.n_attr, nx * nz
+    alg = 2 * (32 + 8 * A) * n + 16 * (C + 1) + 8 * ((nx + 1) * nz + nx * (nz + 1))
+    avg = float(np.mean(per))
+    copy_gbs = copy_bandwidth_gbs()
+    achieved = alg / avg / 1e9
+    flags = int(status.item()) & 0xFFFFFFFF
+    line = {
+        "metric": "super-droplet steps/s (displacement + cell re-segmentation)",
+        "value": n * args.steps / total_s, "unit": "SD-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (Poisson cell sizes, uniform positions, single-eddy face Courant numbers)",
+        "config": {"workload": "displace_grid256x256_single_eddy_A6", "cells": C, "sd_slots": n,
+                   "n_attr": A, "courant_max": float(max(np.abs(cx).max(), np.abs(cz).max())),
+                   "parallelism": "1 GPU, one wavefront per cell"},
+        "roofline": {"bound": "hbm", "kernel": "sdm_displace (k_disp_count, k_disp_offsets, "
+                                                 "k_disp_scan, k_disp_scatter, checks)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": avg * 1e3,
+                     "median_launch_ms": float(np.median(per)) * 1e3, "copy_gbs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs},
+        "status_flags": flags, "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import displacement as D
+
+        ref = (st.xi, st.v, st.attrs, pos, st.cell_off)
+        steps = 3
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ref = D.displace_resegment(nx, nz, cx, cz, *ref[:5])
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": n * steps / dt, "unit": "SD-steps/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"the whole grid ({n} slots), {steps} steps, numpy "
+                                          f"(one thread); {dt:.1f} s"}
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

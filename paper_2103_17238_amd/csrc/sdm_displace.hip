@@ -34,11 +34,13 @@
 
 #include "../../include/sdm.h"
 
-namespace {
+namespace sdm {
 
 constexpr int kDispWaves = 4;    // cells per workgroup, one wavefront each
 constexpr int kOffBlock = 256;   // new cells per block of the size prefix sum
 constexpr int kScanThreads = 1024;
+constexpr int kDispUnroll = 4;    // 64-slot chunks per round of loads
+constexpr int kDispAttrRegs = 8;  // attributes staged in registers per slot
 
 struct DispState {
   int nx, nz, n_attr;
@@ -67,7 +69,7 @@ struct DispState {
 
 // One axis: new fraction and cell shift (clamped to [-1, 1]); bad when the
 // displacement is not below one cell or the old fraction is not in [0, 1).
-__device__ __forceinline__ double axis_step(double w, double lo, double hi, int& shift,
+static __device__ __forceinline__ double axis_step(double w, double lo, double hi, int& shift,
                                             bool& bad) {
   const double d = (1.0 - w) * lo + w * hi;
   bad = !(fabs(d) < 1.0) || !(w >= 0.0 && w < 1.0);
@@ -83,9 +85,9 @@ __device__ __forceinline__ double axis_step(double w, double lo, double hi, int&
   return frac;
 }
 
-__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+static __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-__device__ __forceinline__ int wave_rank_below(uint64_t m, int lane) {
+static __device__ __forceinline__ int wave_rank_below(uint64_t m, int lane) {
   return __popcll(m & ((1ull << lane) - 1ull));
 }
 
@@ -111,7 +113,7 @@ struct Move {
   bool bad;
 };
 
-__device__ __forceinline__ Move move_of(const DispState& S, int64_t j, double cxl, double cxh,
+static __device__ __forceinline__ Move move_of(const DispState& S, int64_t j, double cxl, double cxh,
                                         double czl, double czh) {
   Move m;
   int sx, sz;
@@ -127,26 +129,35 @@ __global__ void __launch_bounds__(64 * kDispWaves) k_disp_count(DispState S) {
   const int C = S.nx * S.nz;
   const int lane = threadIdx.x & 63;
   const int c = blockIdx.x * kDispWaves + (threadIdx.x >> 6);
-  if (c >= C || *S.err) return;  // uniform over the wavefront
+  if (c >= C) return;  // uniform over the wavefront
+  // independent loads first; the offsets are used only if they are valid
+  const uint32_t err = *S.err;
   const int ix = c / S.nz, iz = c - ix * S.nz;
+  const int64_t a = S.off[c], b = S.off[c + 1];
   const double cxl = S.cx[ix * S.nz + iz], cxh = S.cx[(ix + 1) * S.nz + iz];
   const double czl = S.cz[ix * (S.nz + 1) + iz], czh = S.cz[ix * (S.nz + 1) + iz + 1];
-  const int64_t a = S.off[c], b = S.off[c + 1];
+  if (err) return;
   uint32_t mine = 0;  // lane d < 9: droplets moving in direction d
   bool bad = false;
-  for (int64_t j0 = a; j0 < b; j0 += 64) {
-    const int64_t j = j0 + lane;
-    int d = -1;
-    if (j < b) {
-      const Move m = move_of(S, j, cxl, cxh, czl, czh);
-      d = m.d;
-      bad = bad || m.bad;
+  for (int64_t j0 = a; j0 < b; j0 += 64 * kDispUnroll) {
+    int dir[kDispUnroll];
+#pragma unroll
+    for (int u = 0; u < kDispUnroll; ++u) {  // the chunks' loads in flight together
+      const int64_t j = j0 + 64 * u + lane;
+      dir[u] = -1;
+      if (j < b) {
+        const Move m = move_of(S, j, cxl, cxh, czl, czh);
+        dir[u] = m.d;
+        bad = bad || m.bad;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const uint64_t bm = __ballot(d == q);
-      if (lane == q) mine += (uint32_t)__popcll(bm);
-    }
+    for (int u = 0; u < kDispUnroll; ++u)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const uint64_t bm = __ballot(dir[u] == q);
+        if (lane == q) mine += (uint32_t)__popcll(bm);
+      }
   }
   if (lane < 9) S.cnt[(int64_t)c * 9 + lane] = mine;
   if (__any(bad) && lane == 0) atomicOr(S.status, (uint32_t)SDM_FLAG_COURANT);
@@ -218,11 +229,14 @@ __global__ void __launch_bounds__(64 * kDispWaves) k_disp_scatter(DispState S) {
   const int C = S.nx * S.nz;
   const int lane = threadIdx.x & 63;
   const int c = blockIdx.x * kDispWaves + (threadIdx.x >> 6);
-  if (c >= C || *S.err) return;  // uniform over the wavefront
+  if (c >= C) return;  // uniform over the wavefront
+  const uint32_t err = *S.err;
   const int ix = c / S.nz, iz = c - ix * S.nz;
-  if (lane == 0) S.off_out[c] = S.blk_off[c / kOffBlock] + S.local_off[c];
+  const int64_t a = S.off[c], b = S.off[c + 1];
   const double cxl = S.cx[ix * S.nz + iz], cxh = S.cx[(ix + 1) * S.nz + iz];
   const double czl = S.cz[ix * (S.nz + 1) + iz], czh = S.cz[ix * (S.nz + 1) + iz + 1];
+  if (err) return;
+  if (lane == 0) S.off_out[c] = S.blk_off[c / kOffBlock] + S.local_off[c];
   // lane q < 9: next free slot of direction q (its new cell's start, plus
   // this cell's start inside it, plus the droplets already placed)
   int64_t next = 0;
@@ -231,56 +245,77 @@ __global__ void __launch_bounds__(64 * kDispWaves) k_disp_scatter(DispState S) {
     const int t = jx * S.nz + jz;
     next = S.blk_off[t / kOffBlock] + (int64_t)S.local_off[t] + S.base[(int64_t)t * 9 + (8 - lane)];
   }
-  const int64_t a = S.off[c], b = S.off[c + 1];
   const int64_t n = S.n_slots;
   const int A = S.n_attr;
-  for (int64_t j0 = a; j0 < b; j0 += 64) {
-    const int64_t j = j0 + lane;
-    const bool on = j < b;
-    Move m{0.0, 0.0, -1, false};
-    long long x = 0;
-    double vv = 0.0;
-    if (on) {
-      x = S.xi[j];
-      vv = S.v[j];
-      m = move_of(S, j, cxl, cxh, czl, czh);
+  // kDispUnroll chunks of 64 slots per round: every load of the round is
+  // issued before the first store (the bandwidth comes from loads in flight)
+  for (int64_t j0 = a; j0 < b; j0 += 64 * kDispUnroll) {
+    long long xr[kDispUnroll];
+    double vr[kDispUnroll];
+    double ar[kDispUnroll][kDispAttrRegs];
+    Move mr[kDispUnroll];
+#pragma unroll
+    for (int u = 0; u < kDispUnroll; ++u) {
+      const int64_t j = j0 + 64 * u + lane;
+      mr[u] = Move{0.0, 0.0, -1, false};
+      xr[u] = 0;
+      vr[u] = 0.0;
+      if (j < b) {
+        xr[u] = S.xi[j];
+        vr[u] = S.v[j];
+#pragma unroll
+        for (int e = 0; e < kDispAttrRegs; ++e)
+          if (e < A) ar[u][e] = S.attrs[(int64_t)e * n + j];
+        mr[u] = move_of(S, j, cxl, cxh, czl, czh);
+      }
     }
-    int rank = 0;
-    uint32_t adv = 0;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const uint64_t bm = __ballot(m.d == q);
-      if (m.d == q) rank = wave_rank_below(bm, lane);
-      if (lane == q) adv = (uint32_t)__popcll(bm);
-    }
-    const long long start = __shfl((long long)next, on ? m.d : 0);
-    next += adv;
-    if (on) {
-      const int64_t dst = start + rank;
-      S.xi_out[dst] = x;
-      S.v_out[dst] = vv;
-      S.pos_out[dst] = m.wx;
-      S.pos_out[n + dst] = m.wz;
-      for (int q = 0; q < A; q += 4) {  // four loads in flight, then four stores
-        double t[4];
+    for (int u = 0; u < kDispUnroll; ++u) {
+      const int64_t j = j0 + 64 * u + lane;
+      const bool on = j < b;
+      const Move m = mr[u];
+      int rank = 0;  // among this chunk's droplets going the same way
+      uint32_t adv = 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (q + e < A) t[e] = S.attrs[(int64_t)(q + e) * n + j];
+      for (int q = 0; q < 9; ++q) {
+        const uint64_t bm = __ballot(m.d == q);
+        if (m.d == q) rank = wave_rank_below(bm, lane);
+        if (lane == q) adv = (uint32_t)__popcll(bm);
+      }
+      const long long start = __shfl((long long)next, on ? m.d : 0);
+      next += adv;
+      if (on) {
+        const int64_t dst = start + rank;
+        S.xi_out[dst] = xr[u];
+        S.v_out[dst] = vr[u];
+        S.pos_out[dst] = m.wx;
+        S.pos_out[n + dst] = m.wz;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (q + e < A) S.attrs_out[(int64_t)(q + e) * n + dst] = t[e];
+        for (int e = 0; e < kDispAttrRegs; ++e)
+          if (e < A) S.attrs_out[(int64_t)e * n + dst] = ar[u][e];
+        for (int q = kDispAttrRegs; q < A; ++q)  // attributes beyond the staged ones
+          S.attrs_out[(int64_t)q * n + dst] = S.attrs[(int64_t)q * n + j];
       }
     }
   }
 }
 
-}  // namespace
+// fills n words with zero (a kernel, so the call can sit in a captured graph)
+__global__ void k_disp_zero(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+}  // namespace sdm
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 namespace {
 
+using sdm::kDispWaves;
+using sdm::kOffBlock;
+using sdm::kScanThreads;
 constexpr size_t kAlignD = 256;
 inline size_t up(size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; }
 
@@ -291,11 +326,6 @@ size_t ws_bytes(int64_t C) {
          up(sizeof(int64_t) * (size_t)nblk);
 }
 
-// fills n words with zero (a kernel, so the call can sit in a captured graph)
-__global__ void k_disp_zero(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
 
 bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
@@ -334,7 +364,7 @@ sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t work
   if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlignD) return SDM_EINVAL;
   if (workspace_bytes < ws_bytes(C)) return SDM_ENOMEM;
 
-  DispState S{};
+  sdm::DispState S{};
   S.nx = g->nx;
   S.nz = g->nz;
   S.n_attr = g->n_attr;
@@ -368,12 +398,12 @@ sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t work
 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const unsigned cells_grid = (unsigned)((C + kDispWaves - 1) / kDispWaves);
-  hipLaunchKernelGGL(k_disp_zero, dim3(1), dim3(64), 0, st, S.err, 1);
-  hipLaunchKernelGGL(k_disp_check, dim3((unsigned)((C + 1 + 255) / 256)), dim3(256), 0, st, S);
-  hipLaunchKernelGGL(k_disp_count, dim3(cells_grid), dim3(64 * kDispWaves), 0, st, S);
-  hipLaunchKernelGGL(k_disp_offsets, dim3((unsigned)nblk), dim3(kOffBlock), 0, st, S);
-  hipLaunchKernelGGL(k_disp_scan, dim3(1), dim3(kScanThreads), 0, st, S, (int)nblk);
-  hipLaunchKernelGGL(k_disp_scatter, dim3(cells_grid), dim3(64 * kDispWaves), 0, st, S);
+  hipLaunchKernelGGL(sdm::k_disp_zero, dim3(1), dim3(64), 0, st, S.err, 1);
+  hipLaunchKernelGGL(sdm::k_disp_check, dim3((unsigned)((C + 1 + 255) / 256)), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(sdm::k_disp_count, dim3(cells_grid), dim3(64 * kDispWaves), 0, st, S);
+  hipLaunchKernelGGL(sdm::k_disp_offsets, dim3((unsigned)nblk), dim3(kOffBlock), 0, st, S);
+  hipLaunchKernelGGL(sdm::k_disp_scan, dim3(1), dim3(kScanThreads), 0, st, S, (int)nblk);
+  hipLaunchKernelGGL(sdm::k_disp_scatter, dim3(cells_grid), dim3(64 * kDispWaves), 0, st, S);
   return hipGetLastError() == hipSuccess ? SDM_OK : SDM_EDEVICE;
 }
 

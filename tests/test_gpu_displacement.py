@@ -67,7 +67,8 @@ def _check(B, nx, nz, cx, cz, xi, v, attrs, pos, off, want_flags=0):
 
 
 @pytest.mark.parametrize("nx,nz,max_sd,A,seed", [(5, 7, 70, 3, 0), (3, 3, 200, 0, 1),
-                                                 (17, 4, 300, 6, 2), (40, 33, 9, 1, 3)])
+                                                 (17, 4, 300, 6, 2), (40, 33, 9, 1, 3),
+                                                 (9, 5, 600, 11, 4), (6, 6, 40, 16, 5)])
 def test_random_flow_parity(B, nx, nz, max_sd, A, seed):
     """Random face Courant numbers in (-0.9, 0.9): every direction and the
     periodic wrap; uneven cells (empty ones, several 64-slot chunks)."""
