@@ -63,6 +63,24 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+def displace_source_sha():
+    with open(os.path.join(ROOT, "paper_2103_17238_amd", "csrc", "sdm_displace.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def displace_traffic_from_profiles():
+    """HBM bytes per displacement step from the committed rocprofv3 --pmc
+    summary, if it was taken on the current source; else None."""
+    path = os.path.join(PROFILES, "k_disp_grid256_single_eddy_pmc.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("displace_source_sha") != displace_source_sha():
+        return None
+    return (d["fetch_kib_per_step"] + d["write_kib_per_step"]) * 1024.0
+
+
 CLASS_CAPS = (64, 128, 256, 384, 512)
 
 
@@ -481,7 +499,7 @@ def displace_bench(args):
         "roofline": {"bound": "hbm", "kernel": "sdm_displace (k_disp_count, k_disp_offsets, "
                                                  "k_disp_scan, k_disp_scatter, checks)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": displace_traffic_from_profiles(),
                      "alg_bytes_per_launch": alg, "avg_launch_ms": avg * 1e3,
                      "median_launch_ms": float(np.median(per)) * 1e3, "copy_gbs": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs},

@@ -44,3 +44,19 @@ def test_traffic_summary_is_consistent():
             assert got is None
     assert bench.traffic_from_profiles("k_cells", "grid256", 0, {"wave_class_mask": 0x1F,
                                                                  "waves_per_cell": 8}) is None
+
+
+def test_displacement_traffic_summary_is_consistent():
+    d = json.load(open(os.path.join(bench.PROFILES, "k_disp_grid256_single_eddy_pmc.json")))
+    cp = d["copy_probe"]
+    assert abs(d["fetch_scale"] - cp["bytes"] / 1024 / cp["fetch_kib_raw"]) < 1e-9
+    assert abs(d["write_scale"] - cp["bytes"] / 1024 / cp["write_kib_raw"]) < 1e-9
+    f = sum(k["fetch_kib_per_dispatch_raw"] * k["per_step"] for k in d["kernels"])
+    w = sum(k["write_kib_per_dispatch_raw"] * k["per_step"] for k in d["kernels"])
+    assert abs(d["fetch_kib_per_step"] - f * d["fetch_scale"]) < 1
+    assert abs(d["write_kib_per_step"] - w * d["write_scale"]) < 1
+    got = bench.displace_traffic_from_profiles()
+    if d["displace_source_sha"] == bench.displace_source_sha():
+        assert got == (d["fetch_kib_per_step"] + d["write_kib_per_step"]) * 1024.0
+    else:
+        assert got is None
