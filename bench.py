@@ -250,7 +250,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="grid256",
-                    choices=["grid256", "grid64", "golovin", "geometric", "serving", "displace"])
+                    choices=["grid256", "grid64", "golovin", "geometric", "serving", "displace",
+                             "kinematic"])
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--mask", type=lambda x: int(x, 0), default=None,
                     help="fixed class mask (skips the autotuner; e.g. 0x18)")
@@ -295,6 +296,8 @@ def main():
         return serve_bench(args)
     if args.workload == "displace":
         return displace_bench(args)
+    if args.workload == "kinematic":
+        return kinematic_bench(args)
     state, workload = make_state(args.workload)
     host_state = state.copy()
     sim = B.Sim(state)
@@ -520,6 +523,71 @@ def displace_bench(args):
                                           f"(one thread); {dt:.1f} s"}
     else:
         line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+def kinematic_bench(args):
+    """Coalescence with displacement on the 256 x 256 grid: per step one
+    sdm_displace (single-eddy flow), one sdm_rebind (the launch tables
+    rewritten on the device for the new layout; one stream synchronisation)
+    and one coalescence step.  Reports the three parts' times.  Default shape
+    0x18 (cells in the 384-slot class): cells of about 256 slots keep room to
+    grow, so the rebind stays on the device."""
+    import numpy as np
+    import torch
+
+    from paper_2103_17238_amd import binding as B
+    from paper_2103_17238_amd import inputs as I
+
+    st = I.grid_256x256()
+    nx = nz = 256
+    cx, cz = I.single_eddy_courant(nx, nz)
+    sim = B.Sim(st, any_layout=True)
+    t = B.sdm_get_tuning(sim.handle)
+    t.wave_class_mask = args.mask if args.mask is not None else 0x18
+    t.waves_per_cell = args.waves if args.waves else 1
+    B.sdm_set_tuning(sim.handle, t)
+    kin = B.Kinematic2D(sim, nx, nz, cx, cz, I.positions(st.n_slots))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        kin.step(stream)
+        sim.step(1, stream)
+    torch.cuda.synchronize()
+    t_disp = t_rebind = t_coal = 0.0
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        kin.displace(stream)
+        e[1].record(stream)
+        h0 = time.perf_counter()
+        kin.rebind(stream)  # device-side table refresh, one stream synchronisation
+        t_rebind += time.perf_counter() - h0
+        e2 = torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        sim.step(1, stream)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        t_disp += e[0].elapsed_time(e[1]) / 1e3
+        t_coal += e2.elapsed_time(e[2]) / 1e3
+    wall = time.perf_counter() - w0
+    stats = B.sdm_stats(sim.handle)
+    line = {
+        "metric": "super-droplet steps/s (displacement + re-plan + coalescence)",
+        "value": st.n_slots * args.steps / wall, "unit": "SD-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (grid of the coalescence benchmark, uniform positions, single eddy)",
+        "config": {"workload": "kinematic_grid256x256_single_eddy_geometric_adaptive_A6",
+                   "cells": nx * nz, "sd_slots": st.n_slots,
+                   "tuning": B.sdm_get_tuning(sim.handle).as_dict(),
+                   "parallelism": "1 GPU"},
+        "parts_ms_per_step": {"displace": t_disp / args.steps * 1e3,
+                              "rebind": t_rebind / args.steps * 1e3,
+                              "coalescence": t_coal / args.steps * 1e3},
+        "status_flags": kin.flags(), "colliding_pairs": stats["colliding_pairs"],
+        "roofline": None, "cpu_baseline": None,
+    }
     print(json.dumps(line), flush=True)
 
 

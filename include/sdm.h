@@ -210,10 +210,16 @@ const char* sdm_strerror(sdm_status st);
  * Re-point a simulation at new state arrays of the same n_slots and n_cells
  * (for instance the output of sdm_displace, whose cell sizes differ) and
  * re-plan its launches.  The step counter, tuning, statistics and status are
- * kept.  Copies cell_off to the host (synchronises `stream`) and validates it
- * like sdm_init; SDM_ENOMEM if the new layout needs more workspace than the
- * handle was given (size it with sdm_workspace_bytes(cfg, NULL) to allow any
- * layout).  A batch containing s must be re-created afterwards.
+ * kept.  When the plan holds only cells of up to 512 slots and no gamma sink
+ * is set, a few kernels rewrite the launch tables from the new offsets on the
+ * device and the call synchronises `stream` once to read back two words;
+ * if a cell outgrew its size class, slots landed in a cell that had none, or
+ * the offsets are not a valid layout, it falls back to the host re-plan:
+ * cell_off is copied to the host and validated like in sdm_init.  Returns
+ * SDM_EINVAL for an invalid layout (the handle keeps its old one), SDM_ENOMEM
+ * if the new layout needs more workspace than the handle was given (size it
+ * with sdm_workspace_bytes(cfg, NULL) to allow any layout).  A batch
+ * containing s must be re-created afterwards.
  */
 sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const int64_t* cell_off,
                       void* stream);

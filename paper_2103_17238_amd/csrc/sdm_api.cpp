@@ -20,6 +20,7 @@
 
 #include "../../include/sdm.h"
 #include "sdm_internal.hpp"
+#include "sdm_refresh.hpp"
 
 using sdm::BigBucket;
 using sdm::BigChunk;
@@ -65,7 +66,10 @@ struct sdm_sim {
   double* v = nullptr;
   double* attrs = nullptr;
   const int64_t* cell_off = nullptr;
-  std::vector<int64_t> off;  // host copy of cell_off
+  // host copy of cell_off; stale after a device-side rebind until a host
+  // path needs it (fresh_offsets)
+  mutable std::vector<int64_t> off;
+  mutable bool off_stale = false;
   uint32_t step = 0;
   uint32_t limit = 0xFFFFFFFFu;
   sdm_tuning tuning = default_tuning();
@@ -76,8 +80,25 @@ struct sdm_sim {
   uint32_t* d_status = nullptr;
   unsigned long long* d_stats = nullptr;
   int64_t* d_pair_base = nullptr;
+  unsigned long long* d_rebind = nullptr;  // two result words of the device-side rebind
   Plan* plan = nullptr;
 };
+
+static sdm_status rebind_host(sdm_sim* s, int64_t* xi, double* v, double* attrs,
+                              const int64_t* cell_off, hipStream_t st);
+
+// Refreshes the host copy of the offsets after device-side rebinds.
+static bool fresh_offsets(const sdm_sim* s) {
+  if (!s->off_stale) return true;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(s->off.data(), s->cell_off, sizeof(int64_t) * s->off.size(),
+                hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  s->off_stale = false;
+  return true;
+}
 
 // ---------------------------------------------------------------------------
 // Launch plan over a list of simulations
@@ -303,6 +324,8 @@ static size_t lds_block_limit() {
 
 // (Re)build the plan tables for its members and upload them; syncs `st` first.
 static sdm_status plan_setup(Plan* p, hipStream_t st) {
+  for (auto* m : p->members)
+    if (!fresh_offsets(m)) return SDM_EDEVICE;
   p->T = Tables();
   build_tables(p->members, p->tuning, p->T);
   if (p->T.adaptive_big) return SDM_EINVAL;  // adaptive mode needs cells <= mid_max_slots
@@ -425,7 +448,7 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
 // Simulation handle
 // ---------------------------------------------------------------------------
 static size_t sim_region_bytes(int32_t n_cells) {
-  return align_up(sizeof(uint32_t)) +
+  return align_up(sizeof(uint32_t)) + align_up(2 * sizeof(unsigned long long)) +
          align_up(sizeof(unsigned long long) * sdm::kStatSlots * sdm::kStatFields) +
          align_up(sizeof(int64_t) * ((size_t)n_cells + 1));
 }
@@ -549,6 +572,8 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
   s->ws_bytes = workspace_bytes;
   s->d_status = reinterpret_cast<uint32_t*>(w);
   w += align_up(sizeof(uint32_t));
+  s->d_rebind = reinterpret_cast<unsigned long long*>(w);
+  w += align_up(2 * sizeof(unsigned long long));
   s->d_stats = reinterpret_cast<unsigned long long*>(w);
   w += align_up(sizeof(unsigned long long) * sdm::kStatSlots * sdm::kStatFields);
   s->d_pair_base = reinterpret_cast<int64_t*>(w);
@@ -658,6 +683,16 @@ sdm_status sdm_set_step_limit(sdm_sim* s, uint32_t limit) {
 
 sdm_status sdm_debug_gamma_sink(sdm_sim* s, int64_t* dev_buf, int64_t capacity) {
   if (!s) return SDM_EINVAL;
+  if (dev_buf && s->off_stale) {  // the pair bases follow the current layout
+    if (!fresh_offsets(s)) return SDM_EDEVICE;
+    std::vector<int64_t> pb((size_t)s->cfg.n_cells + 1, 0);
+    for (int c = 0; c < s->cfg.n_cells; ++c) pb[c + 1] = pb[c] + (s->off[c + 1] - s->off[c]) / 2;
+    if (hipMemcpy(s->d_pair_base, pb.data(), sizeof(int64_t) * pb.size(),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      return SDM_EDEVICE;
+    }
+  }
   if (dev_buf) {
     int64_t pairs = 0;
     for (int c = 0; c < s->cfg.n_cells; ++c) pairs += (s->off[c + 1] - s->off[c]) / 2;
@@ -690,6 +725,45 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
   if (cfg.n_slots > 0 && (!xi || !v)) return SDM_EINVAL;
   if (cfg.n_attr > 0 && cfg.n_slots > 0 && !attrs) return SDM_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // Device-side refresh when the plan has only workgroup-per-cell tasks and
+  // no gamma sink: rewrite the tasks from the new offsets, then read back
+  // two words; if a cell outgrew its class or slots sit in a cell without a
+  // task, fall through to the host re-plan below.
+  const sdm::PlanDev& pd = s->plan->dev;
+  bool only_wave = pd.n_big == 0 && !s->sink;
+  for (int k = 0; k < sdm::kNumMid; ++k) only_wave = only_wave && pd.n_mid[k] == 0;
+  if (only_wave) {
+    unsigned long long w[2] = {1ull, 0ull};
+    if (sdm::launch_refresh(pd, cell_off, cfg.n_cells, cfg.n_slots, xi, v, s->d_rebind, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(w, s->d_rebind, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      return SDM_EDEVICE;
+    }
+    if (w[0] == 0 && w[1] == (unsigned long long)cfg.n_slots) {
+      s->xi = xi;
+      s->v = v;
+      s->attrs = cfg.n_attr > 0 ? attrs : nullptr;
+      s->cell_off = cell_off;
+      s->off_stale = true;
+      s->plan->counter = s->step;
+      return SDM_OK;  // the descriptor follows at the next step (plan_refresh)
+    }
+  }
+  // host re-plan; the device pass above may have rewritten part of the
+  // tables, so a rejected layout re-plans the old one before returning
+  const sdm_status r = rebind_host(s, xi, v, attrs, cell_off, st);
+  if (r != SDM_OK && only_wave) {
+    const sdm_status r2 = plan_setup(s->plan, st);
+    if (r2 != SDM_OK) return r2;
+  }
+  return r;
+}
+
+static sdm_status rebind_host(sdm_sim* s, int64_t* xi, double* v, double* attrs,
+                              const int64_t* cell_off, hipStream_t st) {
+  const sdm_config& cfg = s->cfg;
   std::vector<int64_t> off((size_t)cfg.n_cells + 1);
   if (hipStreamSynchronize(st) != hipSuccess ||
       hipMemcpy(off.data(), cell_off, sizeof(int64_t) * off.size(), hipMemcpyDeviceToHost) !=
@@ -715,6 +789,7 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
   s->attrs = cfg.n_attr > 0 ? attrs : nullptr;
   s->cell_off = cell_off;
   s->off.swap(off);
+  s->off_stale = false;
   s->plan->counter = s->step;
   return plan_setup(s->plan, st);
 }
@@ -736,7 +811,7 @@ size_t sdm_batch_workspace_bytes(sdm_sim* const* sims, int32_t n) {
   if (!sims || n < 1) return 0;
   std::vector<sdm_sim*> ms(sims, sims + n);
   for (auto* s : ms)
-    if (!s) return 0;
+    if (!s || !fresh_offsets(s)) return 0;
   return plan_bytes_worst(ms);
 }
 
@@ -872,7 +947,7 @@ static void cache_store(const char* path, const std::string& key, const sdm_tuni
 }
 
 extern "C" size_t sdm_autotune_scratch_bytes(const sdm_sim* s) {
-  if (!s) return 0;
+  if (!s || !fresh_offsets(s)) return 0;
   const size_t ns = (size_t)s->cfg.n_slots;
   return align_up(ns * 8) + align_up(ns * 8) + align_up(ns * 8 * (size_t)s->cfg.n_attr) +
          sim_region_bytes(s->cfg.n_cells) + plan_bytes_for(&s->cfg, s->off.data());
@@ -882,6 +957,7 @@ extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_byt
                                    int32_t trial_steps, const char* cache_path,
                                    sdm_tuning* chosen, void* stream) {
   if (!s || trial_steps < 1) return SDM_EINVAL;
+  if (!fresh_offsets(s)) return SDM_EDEVICE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const std::string key = tune_key(s);
   sdm_tuning best{};

@@ -198,6 +198,54 @@ def test_coupled_with_coalescence(B, orc, adaptive):
     sim.close()
 
 
+@pytest.mark.parametrize("mask,empty", [(0x10, False), (0x01, False), (0x1F, True)])
+def test_rebind_paths(B, orc, mask, empty):
+    """The re-plan after displacement: 0x10 (every cell in the 512-slot
+    class) always takes the device-side refresh; 0x01 (64-slot class first)
+    makes cells outgrow their class, and empty cells that receive droplets
+    have no task: both fall back to the host re-plan.  A host re-plan
+    (sdm_set_tuning) and the gamma sink after device-side rebinds must see
+    the current layout.  Everything against the oracle, bit for bit."""
+    import torch
+
+    nx, nz = 10, 8
+    say(f"rebind paths mask={mask:#x} empty={empty}")
+    if empty:
+        st = I.random_cells(nx * nz, 90, n_attr=1, rng_seed=21)
+    else:
+        st = I.grid(nx, nz, 60, n_attr=1, kernel=I.GOLOVIN, seed=3)
+    cx, cz = I.random_courant(nx, nz, 0.85, seed=31)
+    pos = I.positions(st.n_slots, seed=32)
+    sim = B.Sim(st, any_layout=True)
+    t = B.sdm_get_tuning(sim.handle)
+    t.wave_class_mask = mask
+    B.sdm_set_tuning(sim.handle, t)
+    kin = B.Kinematic2D(sim, nx, nz, cx, cz, pos)
+    cfg = ocfg(orc, st)
+    xi, v, at, off, p = st.xi.copy(), st.v.copy(), st.attrs.copy(), st.cell_off.copy(), pos
+    for k in range(4):
+        kin.step()
+        xi, v, at, p, off, fl = D.displace_resegment(nx, nz, cx, cz, xi, v, at, p, off)
+        xi, v, at = xi.copy(), v.copy(), np.ascontiguousarray(at)
+        if k == 2:  # a host re-plan on the current layout
+            t.waves_per_cell = 2
+            B.sdm_set_tuning(sim.handle, t)
+        want_log = k == 3
+        if want_log:
+            npairs = int((np.diff(off) // 2).sum())
+            sink = torch.full((2 * npairs,), -7, dtype=torch.int64, device="cuda")
+            B.sdm_debug_gamma_sink(sim.handle, sink)
+        sim.step(1)
+        out = orc.step(cfg, xi, v, at, off, k, want_log=want_log)
+        gx, gv, ga = sim.state()
+        assert np.array_equal(gx, xi) and np.array_equal(gv, v) and np.array_equal(ga, at), k
+        if want_log:
+            torch.cuda.synchronize()
+            assert np.array_equal(sink.cpu().numpy().reshape(-1, 2), out["log"])
+    assert kin.flags() == 0
+    sim.close()
+
+
 def test_rebind_rejects_bad_layout(B):
     import torch
 
