@@ -734,8 +734,17 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
   for (int k = 0; k < sdm::kNumMid; ++k) only_wave = only_wave && pd.n_mid[k] == 0;
   if (only_wave) {
     unsigned long long w[2] = {1ull, 0ull};
+    // the descriptor for the new buffers goes with the same synchronisation
+    // (a failed check re-plans, which rewrites it)
+    Plan* p = s->plan;
+    p->desc[0].xi = xi;
+    p->desc[0].v = v;
+    p->desc[0].attrs = cfg.n_attr > 0 ? attrs : nullptr;
+    p->desc[0].cell_off = cell_off;
     if (sdm::launch_refresh(pd, cell_off, cfg.n_cells, cfg.n_slots, xi, v, s->d_rebind, st) !=
             hipSuccess ||
+        hipMemcpyAsync(const_cast<SimDesc*>(pd.desc), p->desc.data(), sizeof(SimDesc),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess ||
         hipMemcpy(w, s->d_rebind, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) {
       (void)hipGetLastError();

@@ -195,6 +195,11 @@ def test_coupled_with_coalescence(B, orc, adaptive):
     assert kin.flags() == 0
     st2 = B.sdm_stats(sim.handle)
     assert st2["colliding_pairs"] > 0
+    # moments follow the current layout
+    gm = sim.moments()
+    om = orc.moments(cfg, xi, v, at, off)
+    assert np.array_equal(gm["m0"], om["m0"])
+    assert np.allclose(gm["m1"], om["m1"], rtol=1e-12, atol=0)
     sim.close()
 
 
