@@ -440,7 +440,7 @@ def main():
 def displace_bench(args):
     """Displacement + re-segmentation of the 256 x 256 grid (16.8 M slots, 6
     attributes) in the single-eddy flow (20 m cells, w_max 0.6 m/s, dt 1 s):
-    one step = one sdm_displace call (six kernels) from one set of state
+    one step = one sdm_displace call (four kernels) from one set of state
     buffers into the other.  Algorithmic bytes per step: one read and one
     write of every slot's xi, v, attributes and position ((32 + 8 A) x 2 =
     160 B per slot), the cell offsets (16 B per cell) and the face Courant
@@ -500,7 +500,7 @@ def displace_bench(args):
                    "n_attr": A, "courant_max": float(max(np.abs(cx).max(), np.abs(cz).max())),
                    "parallelism": "1 GPU, one wavefront per cell"},
         "roofline": {"bound": "hbm", "kernel": "sdm_displace (k_disp_count, k_disp_offsets, "
-                                                 "k_disp_scan, k_disp_scatter, checks)",
+                                                 "k_disp_scan, k_disp_scatter)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": displace_traffic_from_profiles(),
                      "alg_bytes_per_launch": alg, "avg_launch_ms": avg * 1e3,

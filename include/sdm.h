@@ -250,13 +250,13 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
  * All pointers are device memory owned by the caller; outputs must not
  * overlap inputs.  An input cell_off that is not a valid layout of n_slots
  * raises SDM_FLAG_INVALID_STATE and leaves the outputs unwritten.  Enqueue
- * only (six small kernels, no allocation, no synchronisation).
+ * only (four kernels, no allocation, no synchronisation).
  */
 typedef struct {
   int32_t nx, nz;          /* cells per axis, >= 3 each */
   int32_t n_attr;          /* extra attributes, 0..16 */
   int32_t reserved;        /* must be 0 */
-  int64_t n_slots;         /* 0 .. 2^32 - 1 */
+  int64_t n_slots;         /* 0 .. 2^32 - 2 */
   const double* courant_x; /* [(nx + 1) * nz] */
   const double* courant_z; /* [nx * (nz + 1)] */
   const int64_t* xi;       /* input state, layout as in sdm_init */

@@ -16,13 +16,16 @@
 // to that order.
 //
 // Data path (cells c = ix * nz + iz, one wavefront per cell):
-//   k_disp_check    cell offsets valid (else nothing below runs)
 //   k_disp_count    per cell, droplets leaving towards each of the 9
-//                   neighbour directions (|d| < 1, so at most one cell per axis)
+//                   neighbour directions (|d| < 1, so at most one cell per
+//                   axis); a cell whose offsets do not fit a valid layout is
+//                   marked instead
 //   k_disp_offsets  per new cell: its size, and where each of its 9 source
 //                   cells' droplets start (sources in old cell order); block
-//                   prefix sums of the sizes
-//   k_disp_scan     prefix over the blocks
+//                   prefix sums of the sizes; per block, whether a marked
+//                   cell was seen
+//   k_disp_scan     prefix over the blocks; the error word (nothing below
+//                   writes if it is set)
 //   k_disp_scatter  per old cell: each droplet's new slot = start of its new
 //                   cell + start of its source cell there + its rank among the
 //                   cell's droplets going the same way; copies xi, v, attrs and
@@ -41,6 +44,7 @@ constexpr int kOffBlock = 256;   // new cells per block of the size prefix sum
 constexpr int kScanThreads = 1024;
 constexpr int kDispUnroll = 4;    // 64-slot chunks per round of loads
 constexpr int kDispAttrRegs = 8;  // attributes staged in registers per slot
+constexpr uint32_t kBadCell = 0xFFFFFFFFu;  // count entry of a cell with invalid offsets
 
 struct DispState {
   int nx, nz, n_attr;
@@ -59,7 +63,8 @@ struct DispState {
   int64_t* off_out;
   uint32_t* status;
   // workspace
-  uint32_t* err;        // 1 word: the offsets are not a valid layout
+  uint32_t* err;        // 1 word: the offsets are not a valid layout (set by k_disp_scan)
+  uint32_t* blk_err;    // [ceil(C / kOffBlock)] a block saw a marked cell
   uint32_t* cnt;        // [C][9] droplets of old cell c moving in direction d
   uint32_t* base;       // [C][9] start of source k's droplets inside new cell c
   uint32_t* local_off;  // [C] start of new cell c inside its block
@@ -91,21 +96,6 @@ static __device__ __forceinline__ int wave_rank_below(uint64_t m, int lane) {
   return __popcll(m & ((1ull << lane) - 1ull));
 }
 
-__global__ void __launch_bounds__(256) k_disp_check(DispState S) {
-  const int C = S.nx * S.nz;
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c > C) return;
-  bool bad = false;
-  const int64_t a = S.off[c];
-  if (c == 0) bad = a != 0;
-  if (c == C) bad = a != S.n_slots;
-  if (c < C) bad = bad || S.off[c + 1] < a;
-  if (bad) {
-    atomicOr(S.err, 1u);
-    atomicOr(S.status, (uint32_t)SDM_FLAG_INVALID_STATE);
-  }
-}
-
 // The droplet j of cell (ix, iz): new fractions and direction (sx + 1) * 3 + (sz + 1).
 struct Move {
   double wx, wz;
@@ -130,13 +120,18 @@ __global__ void __launch_bounds__(64 * kDispWaves) k_disp_count(DispState S) {
   const int lane = threadIdx.x & 63;
   const int c = blockIdx.x * kDispWaves + (threadIdx.x >> 6);
   if (c >= C) return;  // uniform over the wavefront
-  // independent loads first; the offsets are used only if they are valid
-  const uint32_t err = *S.err;
   const int ix = c / S.nz, iz = c - ix * S.nz;
   const int64_t a = S.off[c], b = S.off[c + 1];
   const double cxl = S.cx[ix * S.nz + iz], cxh = S.cx[(ix + 1) * S.nz + iz];
   const double czl = S.cz[ix * (S.nz + 1) + iz], czh = S.cz[ix * (S.nz + 1) + iz + 1];
-  if (err) return;
+  // every cell checks its own offsets: together they check the whole layout
+  const bool valid = a >= 0 && a <= b && b <= S.n_slots && (c != 0 || a == 0) &&
+                     (c != C - 1 || b == S.n_slots);
+  if (!valid) {
+    if (lane < 9) S.cnt[(int64_t)c * 9 + lane] = kBadCell;
+    if (lane == 0) atomicOr(S.status, (uint32_t)SDM_FLAG_INVALID_STATE);
+    return;
+  }
   uint32_t mine = 0;  // lane d < 9: droplets moving in direction d
   bool bad = false;
   for (int64_t j0 = a; j0 < b; j0 += 64 * kDispUnroll) {
@@ -170,7 +165,8 @@ __global__ void __launch_bounds__(kOffBlock) k_disp_offsets(DispState S) {
   const int C = S.nx * S.nz;
   const int c = blockIdx.x * kOffBlock + threadIdx.x;
   uint32_t total = 0;
-  if (c < C && !*S.err) {
+  bool marked = false;
+  if (c < C) {
     const int ix = c / S.nz, iz = c - ix * S.nz;
     int src[9];
     uint32_t n[9];
@@ -179,6 +175,7 @@ __global__ void __launch_bounds__(kOffBlock) k_disp_offsets(DispState S) {
       const int jx = wrap(ix + k / 3 - 1, S.nx), jz = wrap(iz + k % 3 - 1, S.nz);
       src[k] = jx * S.nz + jz;
       n[k] = S.cnt[(int64_t)src[k] * 9 + (8 - k)];
+      marked = marked || n[k] == kBadCell;  // the cell itself is source k = 4
       total += n[k];
     }
 #pragma unroll
@@ -201,14 +198,18 @@ __global__ void __launch_bounds__(kOffBlock) k_disp_offsets(DispState S) {
   }
   if (c < C) S.local_off[c] = sh[threadIdx.x] - total;
   if (threadIdx.x == kOffBlock - 1) S.blk_sum[blockIdx.x] = sh[threadIdx.x];
+  const int any = __syncthreads_or(marked ? 1 : 0);
+  if (threadIdx.x == 0) S.blk_err[blockIdx.x] = any ? 1u : 0u;
 }
 
 // One workgroup: exclusive prefix over the block sums; the new n_slots end.
 __global__ void __launch_bounds__(kScanThreads) k_disp_scan(DispState S, int nblk) {
   __shared__ int64_t sh[kScanThreads];
   int64_t carry = 0;
+  int bad = 0;
   for (int b0 = 0; b0 < nblk; b0 += kScanThreads) {
     const int b = b0 + threadIdx.x;
+    if (b < nblk && S.blk_err[b]) bad = 1;
     const int64_t x = b < nblk ? (int64_t)S.blk_sum[b] : 0;
     sh[threadIdx.x] = x;
     __syncthreads();
@@ -222,7 +223,11 @@ __global__ void __launch_bounds__(kScanThreads) k_disp_scan(DispState S, int nbl
     carry += sh[kScanThreads - 1];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && !*S.err) S.off_out[S.nx * S.nz] = carry;
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) {
+    *S.err = bad ? 1u : 0u;  // read by k_disp_scatter, the next kernel
+    if (!bad) S.off_out[S.nx * S.nz] = carry;
+  }
 }
 
 __global__ void __launch_bounds__(64 * kDispWaves) k_disp_scatter(DispState S) {
@@ -300,12 +305,6 @@ __global__ void __launch_bounds__(64 * kDispWaves) k_disp_scatter(DispState S) {
   }
 }
 
-// fills n words with zero (a kernel, so the call can sit in a captured graph)
-__global__ void k_disp_zero(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
 }  // namespace sdm
 
 // ---------------------------------------------------------------------------
@@ -322,7 +321,7 @@ inline size_t up(size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; }
 size_t ws_bytes(int64_t C) {
   const int64_t nblk = (C + kOffBlock - 1) / kOffBlock;
   return up(sizeof(uint32_t)) + 2 * up(sizeof(uint32_t) * 9 * (size_t)C) +
-         up(sizeof(uint32_t) * (size_t)C) + up(sizeof(uint32_t) * (size_t)nblk) +
+         up(sizeof(uint32_t) * (size_t)C) + 2 * up(sizeof(uint32_t) * (size_t)nblk) +
          up(sizeof(int64_t) * (size_t)nblk);
 }
 
@@ -345,7 +344,7 @@ sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t work
                         void* stream) {
   if (!g || g->nx < 3 || g->nz < 3 || (int64_t)g->nx * g->nz > (int64_t)0x7FFFFFFF / 9 ||
       g->n_attr < 0 || g->n_attr > 16 || g->reserved != 0 || g->n_slots < 0 ||
-      g->n_slots > 0xFFFFFFFFLL)
+      g->n_slots >= 0xFFFFFFFFLL)
     return SDM_EINVAL;
   const int64_t C = (int64_t)g->nx * g->nz, n = g->n_slots, A = g->n_attr;
   if (!g->courant_x || !g->courant_z || !g->cell_off || !g->cell_off_out || !g->status)
@@ -394,12 +393,12 @@ sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t work
   w += up(sizeof(uint32_t) * (size_t)C);
   S.blk_sum = reinterpret_cast<uint32_t*>(w);
   w += up(sizeof(uint32_t) * (size_t)nblk);
+  S.blk_err = reinterpret_cast<uint32_t*>(w);
+  w += up(sizeof(uint32_t) * (size_t)nblk);
   S.blk_off = reinterpret_cast<int64_t*>(w);
 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const unsigned cells_grid = (unsigned)((C + kDispWaves - 1) / kDispWaves);
-  hipLaunchKernelGGL(sdm::k_disp_zero, dim3(1), dim3(64), 0, st, S.err, 1);
-  hipLaunchKernelGGL(sdm::k_disp_check, dim3((unsigned)((C + 1 + 255) / 256)), dim3(256), 0, st, S);
   hipLaunchKernelGGL(sdm::k_disp_count, dim3(cells_grid), dim3(64 * kDispWaves), 0, st, S);
   hipLaunchKernelGGL(sdm::k_disp_offsets, dim3((unsigned)nblk), dim3(kOffBlock), 0, st, S);
   hipLaunchKernelGGL(sdm::k_disp_scan, dim3(1), dim3(kScanThreads), 0, st, S, (int)nblk);
