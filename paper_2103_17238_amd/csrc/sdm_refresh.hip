@@ -78,14 +78,14 @@ hipError_t launch_refresh(const PlanDev& p, const int64_t* off, int n_cells, int
   for (int k = 0; k < kNumClasses; ++k) {
     const int cap = class_cap(k);
     const int nw = p.n_wave[k], na = p.n_wave[k] - p.n_plain[k];
+    const unsigned gw = (unsigned)((nw + kRefreshBlock - 1) / kRefreshBlock);
+    const unsigned ga = (unsigned)((na + kRefreshBlock - 1) / kRefreshBlock);
     if (nw > 0)
-      hipLaunchKernelGGL(k_refresh_tasks, dim3((unsigned)((nw + kRefreshBlock - 1) / kRefreshBlock)),
-                         dim3(kRefreshBlock), 0, st, p.wave_tasks[k], nw, cap, off, C, n_slots, xi,
-                         v, w, 1);
+      hipLaunchKernelGGL(k_refresh_tasks, dim3(gw), dim3(kRefreshBlock), 0, st, p.wave_tasks[k],
+                         nw, cap, off, C, n_slots, xi, v, w, 1);
     if (na > 0)
-      hipLaunchKernelGGL(k_refresh_tasks, dim3((unsigned)((na + kRefreshBlock - 1) / kRefreshBlock)),
-                         dim3(kRefreshBlock), 0, st, p.wave_alt[k], na, cap, off, C, n_slots, xi,
-                         v, w, 0);
+      hipLaunchKernelGGL(k_refresh_tasks, dim3(ga), dim3(kRefreshBlock), 0, st, p.wave_alt[k], na,
+                         cap, off, C, n_slots, xi, v, w, 0);
   }
   return hipGetLastError();
 }
