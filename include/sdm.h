@@ -199,7 +199,8 @@ sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_bytes, int32_t
 size_t sdm_batch_workspace_bytes(sdm_sim* const* sims, int32_t n);
 sdm_status sdm_batch_create(sdm_batch** out, sdm_sim* const* sims, int32_t n, void* workspace,
                             size_t workspace_bytes, void* stream);
-/* Advance every member n_steps (each member honours its own step limit). */
+/* Advance every member n_steps (each member honours its own step limit).
+ * SDM_ESTATE if a member was re-pointed by sdm_rebind since the batch was made. */
 sdm_status sdm_batch_step(sdm_batch* b, int32_t n_steps, void* stream);
 void sdm_batch_free(sdm_batch* b);
 
@@ -219,7 +220,8 @@ const char* sdm_strerror(sdm_status st);
  * SDM_EINVAL for an invalid layout (the handle keeps its old one), SDM_ENOMEM
  * if the new layout needs more workspace than the handle was given (size it
  * with sdm_workspace_bytes(cfg, NULL) to allow any layout).  A batch
- * containing s must be re-created afterwards.
+ * containing s must be re-created afterwards: sdm_batch_step returns
+ * SDM_ESTATE for a batch whose members were re-pointed after it was made.
  */
 sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const int64_t* cell_off,
                       void* stream);

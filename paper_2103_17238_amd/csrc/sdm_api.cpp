@@ -81,6 +81,7 @@ struct sdm_sim {
   unsigned long long* d_stats = nullptr;
   int64_t* d_pair_base = nullptr;
   unsigned long long* d_rebind = nullptr;  // two result words of the device-side rebind
+  uint32_t layout_gen = 0;                 // bumped by every sdm_rebind
   Plan* plan = nullptr;
 };
 
@@ -757,7 +758,8 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
       s->cell_off = cell_off;
       s->off_stale = true;
       s->plan->counter = s->step;
-      return SDM_OK;  // the descriptor follows at the next step (plan_refresh)
+      s->layout_gen += 1;
+      return SDM_OK;
     }
   }
   // host re-plan; the device pass above may have rewritten part of the
@@ -800,6 +802,7 @@ static sdm_status rebind_host(sdm_sim* s, int64_t* xi, double* v, double* attrs,
   s->off.swap(off);
   s->off_stale = false;
   s->plan->counter = s->step;
+  s->layout_gen += 1;
   return plan_setup(s->plan, st);
 }
 
@@ -814,6 +817,7 @@ void sdm_free(sdm_sim* s) {
 // ---------------------------------------------------------------------------
 struct sdm_batch {
   Plan plan;
+  std::vector<uint32_t> gens;  // members' layout generations the tables were built for
 };
 
 size_t sdm_batch_workspace_bytes(sdm_sim* const* sims, int32_t n) {
@@ -846,12 +850,15 @@ sdm_status sdm_batch_create(sdm_batch** out, sdm_sim* const* sims, int32_t n, vo
     delete b;
     return r;
   }
+  for (auto* s : b->plan.members) b->gens.push_back(s->layout_gen);
   *out = b;
   return SDM_OK;
 }
 
 sdm_status sdm_batch_step(sdm_batch* b, int32_t n_steps, void* stream) {
   if (!b) return SDM_EINVAL;
+  for (size_t i = 0; i < b->gens.size(); ++i)  // a member was re-pointed since
+    if (b->plan.members[i]->layout_gen != b->gens[i]) return SDM_ESTATE;
   return plan_step(&b->plan, n_steps, reinterpret_cast<hipStream_t>(stream));
 }
 

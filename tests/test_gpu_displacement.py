@@ -251,6 +251,33 @@ def test_rebind_paths(B, orc, mask, empty):
     sim.close()
 
 
+def test_batch_refuses_after_rebind(B):
+    """A batch made before a member's rebind refuses to step (its tables
+    point at the old buffers); a batch made afterwards steps."""
+    import torch
+
+    nx, nz = 5, 4
+    st = I.grid(nx, nz, 30, kernel=I.GOLOVIN)
+    sims = [B.Sim(st, any_layout=True), B.Sim(st, any_layout=True)]
+    handles = [s.handle for s in sims]
+    ws = B.workspace_tensor(B.sdm_batch_workspace_bytes(handles))
+    batch = B.sdm_batch_create(handles, ws)
+    B.sdm_batch_step(batch, 1)
+    cx, cz = I.random_courant(nx, nz, 0.8, seed=41)
+    kin = B.Kinematic2D(sims[0], nx, nz, cx, cz, I.positions(st.n_slots, seed=42))
+    kin.step()
+    with pytest.raises(B.SdmError):
+        B.sdm_batch_step(batch, 1)
+    B.sdm_batch_free(batch)
+    ws2 = B.workspace_tensor(B.sdm_batch_workspace_bytes(handles))
+    batch2 = B.sdm_batch_create(handles, ws2)
+    B.sdm_batch_step(batch2, 1)
+    torch.cuda.synchronize()
+    B.sdm_batch_free(batch2)
+    for s in sims:
+        s.close()
+
+
 def test_rebind_rejects_bad_layout(B):
     import torch
 
