@@ -11,7 +11,10 @@ coalescence (section "API in brief") and couples the particles to a prescribed
 (prescribed-flow) examples"), but gives no scheme.  Readings taken here:
 
   - the domain is nx x nz cells, cell index c = ix * nz + iz, periodic in both
-    directions;
+    directions; along an axis of one cell a droplet that crosses a face
+    re-enters the same cell (its shift is 0), and along an axis of two cells
+    both directions lead to the other cell (its shift is taken as +1), so a
+    1D column (nx = 1) is a grid like any other;
   - a super-droplet carries its position inside its cell as two fractions
     (wx, wz) in [0, 1);
   - the flow is given as Courant numbers on cell faces (a staggered grid):
@@ -63,6 +66,16 @@ def cell_coords(cell_off, nz):
     return c // nz, c % nz
 
 
+def periodic_shift(shift, n_axis):
+    """The shift along an axis of n_axis cells: 0 if the axis has one cell,
+    +1 for any move if it has two (both neighbours are the same cell)."""
+    if n_axis == 1:
+        return np.zeros_like(shift)
+    if n_axis == 2:
+        return (shift != 0).astype(shift.dtype)
+    return shift
+
+
 def displace(nx, nz, cx, cz, pos, cell_off):
     """One displacement step.  pos: (2, n) fractions (x row, z row).
 
@@ -75,6 +88,8 @@ def displace(nx, nz, cx, cz, pos, cell_off):
     ix, iz = cell_coords(cell_off, nz)
     wx, sx, bx = axis_step(pos[0], cx[ix, iz], cx[ix + 1, iz])
     wz, sz, bz = axis_step(pos[1], cz[ix, iz], cz[ix, iz + 1])
+    sx = periodic_shift(sx, nx)
+    sz = periodic_shift(sz, nz)
     jx = (ix + sx) % nx
     jz = (iz + sz) % nz
     flags = ST_COURANT if (bx.any() or bz.any()) else 0

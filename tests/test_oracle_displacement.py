@@ -172,3 +172,29 @@ def test_position_out_of_range_flags():
     pos[1, 4] = 1.0
     cx, cz = I.uniform_courant(nx, nz, 0.0, 0.0)
     assert D.displace(nx, nz, cx, cz, pos, off)[2] == D.ST_COURANT
+
+
+@pytest.mark.parametrize("nx,nz", [(1, 7), (2, 5), (4, 1), (2, 2), (1, 1)])
+def test_narrow_axes(nx, nz):
+    """Axes of one or two cells: every droplet lands in the cell the periodic
+    domain puts it in (closed form of a uniform flow), and the slot order is
+    the stable order by new cell (brute force)."""
+    counts = np.random.default_rng(nx * 10 + nz).integers(0, 30, size=nx * nz)
+    xi, v, attrs, off = _state(counts, 1, seed=7)
+    rng = np.random.default_rng(8)
+    pos = rng.uniform(0.02, 0.98, size=(2, xi.size))
+    ux, uz = 0.6, -0.7
+    for w, u in ((pos[0], ux), (pos[1], uz)):
+        f = (w + u) % 1.0
+        w[(f < 1e-6) | (f > 1 - 1e-6)] += 0.003
+    cx, cz = I.uniform_courant(nx, nz, ux, uz)
+    new_pos, new_cell, fl = D.displace(nx, nz, cx, cz, pos, off)
+    assert fl == 0
+    c = np.repeat(np.arange(nx * nz), counts)
+    ax = (c // nz + pos[0] + ux) % nx
+    az = (c % nz + pos[1] + uz) % nz
+    assert np.array_equal(new_cell, np.floor(ax).astype(int) * nz + np.floor(az).astype(int))
+    assert np.allclose(new_pos[0], ax - np.floor(ax), atol=1e-12, rtol=0)
+    order, o2 = D.resegment(new_cell, nx * nz)
+    brute = [j for cc in range(nx * nz) for j in range(xi.size) if new_cell[j] == cc]
+    assert order.tolist() == brute
