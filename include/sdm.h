@@ -233,7 +233,9 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
  * ("Kinematic (prescribed-flow) examples") without giving a scheme; this is
  * one explicit first-order step:
  *   - cells c = ix * nz + iz of an nx x nz domain, periodic in x and z,
- *     nx, nz >= 3;
+ *     nx, nz >= 1 (along an axis of one cell a droplet that crosses a face
+ *     re-enters its cell; along an axis of two, both directions lead to the
+ *     other cell: a 1D column is nx = 1);
  *   - pos[2][n_slots] (float64): each droplet's position inside its cell as
  *     fractions wx = pos[0][j], wz = pos[1][j] in [0, 1);
  *   - Courant numbers on cell faces: courant_x[(nx + 1) * nz], entry
@@ -255,7 +257,7 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
  * only (four kernels, no allocation, no synchronisation).
  */
 typedef struct {
-  int32_t nx, nz;          /* cells per axis, >= 3 each */
+  int32_t nx, nz;          /* cells per axis, >= 1 each */
   int32_t n_attr;          /* extra attributes, 0..16 */
   int32_t reserved;        /* must be 0 */
   int64_t n_slots;         /* 0 .. 2^32 - 2 */

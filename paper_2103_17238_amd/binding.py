@@ -411,7 +411,7 @@ class Kinematic2D:
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         nb = sdm_displace_workspace_bytes(nx, nz)
         if nb == 0:
-            raise ValueError("displacement needs nx, nz >= 3")
+            raise ValueError("displacement needs nx, nz >= 1")
         self.ws = workspace_tensor(nb, dev)
 
     def displace(self, stream=None):

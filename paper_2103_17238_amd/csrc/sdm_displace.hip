@@ -92,6 +92,14 @@ static __device__ __forceinline__ double axis_step(double w, double lo, double h
 
 static __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Along an axis of one cell a move re-enters the same cell; along an axis of
+// two both directions reach the one neighbour, taken as +1.  So the groups
+// (source cell, direction) that can be non-empty stay distinct for every
+// destination, even where a destination's nine neighbours repeat cells.
+static __device__ __forceinline__ int periodic_shift(int s, int n_axis) {
+  return n_axis == 1 ? 0 : (n_axis == 2 ? (s != 0 ? 1 : 0) : s);
+}
+
 static __device__ __forceinline__ int wave_rank_below(uint64_t m, int lane) {
   return __popcll(m & ((1ull << lane) - 1ull));
 }
@@ -110,6 +118,8 @@ static __device__ __forceinline__ Move move_of(const DispState& S, int64_t j, do
   bool bx, bz;
   m.wx = axis_step(S.pos[j], cxl, cxh, sx, bx);
   m.wz = axis_step(S.pos[S.n_slots + j], czl, czh, sz, bz);
+  sx = periodic_shift(sx, S.nx);
+  sz = periodic_shift(sz, S.nz);
   m.d = (sx + 1) * 3 + (sz + 1);
   m.bad = bx || bz;
   return m;
@@ -159,8 +169,10 @@ __global__ void __launch_bounds__(64 * kDispWaves) k_disp_count(DispState S) {
 }
 
 // Source k of new cell (ix, iz) sits at offset (k / 3 - 1, k % 3 - 1); its
-// droplets reach the cell by moving in direction 8 - k.  With nx, nz >= 3 the
-// nine sources are distinct cells, and they are placed in old cell order.
+// droplets reach the cell by moving in direction 8 - k.  Sources are placed
+// in old cell order.  Along an axis of one or two cells several k name the
+// same cell; of those only one group can hold droplets (periodic_shift), and
+// a source's start counts strictly smaller cells only, so it is the same.
 __global__ void __launch_bounds__(kOffBlock) k_disp_offsets(DispState S) {
   const int C = S.nx * S.nz;
   const int c = blockIdx.x * kOffBlock + threadIdx.x;
@@ -336,13 +348,13 @@ bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
 extern "C" {
 
 size_t sdm_displace_workspace_bytes(int32_t nx, int32_t nz) {
-  if (nx < 3 || nz < 3 || (int64_t)nx * nz > (int64_t)0x7FFFFFFF / 9) return 0;
+  if (nx < 1 || nz < 1 || (int64_t)nx * nz > (int64_t)0x7FFFFFFF / 9) return 0;
   return ws_bytes((int64_t)nx * nz);
 }
 
 sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t workspace_bytes,
                         void* stream) {
-  if (!g || g->nx < 3 || g->nz < 3 || (int64_t)g->nx * g->nz > (int64_t)0x7FFFFFFF / 9 ||
+  if (!g || g->nx < 1 || g->nz < 1 || (int64_t)g->nx * g->nz > (int64_t)0x7FFFFFFF / 9 ||
       g->n_attr < 0 || g->n_attr > 16 || g->reserved != 0 || g->n_slots < 0 ||
       g->n_slots >= 0xFFFFFFFFLL)
     return SDM_EINVAL;

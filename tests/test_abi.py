@@ -52,8 +52,8 @@ def test_displace_argument_checks():
 
     from paper_2103_17238_amd import binding as B
 
-    assert B.sdm_displace_workspace_bytes(2, 5) == 0
-    assert B.sdm_displace_workspace_bytes(3, 3) > 0
+    assert B.sdm_displace_workspace_bytes(0, 5) == 0
+    assert B.sdm_displace_workspace_bytes(1, 1) > 0
     lib = C.CDLL(B.library_path())
     f = lib.sdm_displace
     f.restype = C.c_int
@@ -72,7 +72,7 @@ def test_displace_argument_checks():
 
     ws = 1 << 45
     good = args()
-    assert f(C.byref(args(nx=2)), ws, 1 << 30, None) == B.SDM_EINVAL
+    assert f(C.byref(args(nx=0)), ws, 1 << 30, None) == B.SDM_EINVAL
     assert f(C.byref(args(A=17)), ws, 1 << 30, None) == B.SDM_EINVAL
     assert f(C.byref(args(reserved=1)), ws, 1 << 30, None) == B.SDM_EINVAL
     assert f(C.byref(args(xi=None)), ws, 1 << 30, None) == B.SDM_EINVAL

@@ -84,6 +84,19 @@ def test_random_flow_parity(B, nx, nz, max_sd, A, seed):
     assert np.diff(got[4]).min() >= 0
 
 
+@pytest.mark.parametrize("nx,nz", [(1, 7), (2, 5), (4, 1), (2, 2), (1, 1), (1, 40)])
+def test_narrow_axes_parity(B, nx, nz):
+    """Axes of one or two cells (a 1D column is nx = 1): random flows that
+    move droplets both ways along every axis."""
+    say(f"displace narrow nx={nx} nz={nz}")
+    rng = np.random.default_rng(nx * 100 + nz)
+    counts = rng.integers(0, 150, size=nx * nz)
+    xi, v, attrs, off = _cells(nx, nz, counts, 2, nx + nz)
+    pos = I.positions(xi.size, seed=nx + 3 * nz)
+    cx, cz = I.random_courant(nx, nz, 0.9, seed=nx + 5 * nz)
+    _check(B, nx, nz, cx, cz, xi, v, attrs, pos, off)
+
+
 def test_zero_flow_and_empty(B):
     nx, nz = 4, 5
     say("displace zero flow")
