@@ -34,4 +34,5 @@ from .oracle import (  # noqa: F401
     probe_mul_add,
     max_threads,
     pair_base,
+    cell_adaptive_trace,
 )

@@ -108,6 +108,9 @@ def lib():
                                           C.c_int64, P]
         L.orc_step.argtypes = [C.POINTER(_Cfg), P, P, P, P, C.c_uint32, P, P, P]
         L.orc_step.restype = C.c_uint32
+        L.orc_cell_adaptive_trace.argtypes = [C.POINTER(_Cfg), P, P, P, C.c_int64, C.c_int32,
+                                              C.c_uint32, C.c_int32, P, P, P, P, P, P]
+        L.orc_cell_adaptive_trace.restype = C.c_int32
         L.orc_moments.argtypes = [C.POINTER(_Cfg), P, P, P, P, P, P, P, P, C.c_int32, P]
         L.orc_probe_mul_add.argtypes = [C.c_double] * 3
         L.orc_probe_mul_add.restype = C.c_double
@@ -228,6 +231,37 @@ def step(cfg: OracleConfig, xi, v, attrs, cell_off, step_index, want_log=False,
     if want_substeps:
         out["substeps"] = sub
     return out
+
+
+def cell_adaptive_trace(cfg: OracleConfig, xi, v, attrs, c, step_index, cap=4096):
+    """One adaptive outer step of a single cell (the whole arrays are the
+    cell), in place, recording every substep.  Returns a list of dicts with
+    dt_left, dt_sub, n_live, clamped and the substep's pair log (rows
+    (a | b << 32, gamma)), and the status bits."""
+    _need(xi, np.int64)
+    _need(v, np.float64)
+    n = xi.size
+    assert cfg.n_slots == n and v.size == n
+    if cfg.n_attr:
+        _need(attrs, np.float64)
+        assert attrs.size == cfg.n_attr * n
+    npair = n // 2
+    dl = np.zeros(cap)
+    ds = np.zeros(cap)
+    nl = np.zeros(cap, dtype=np.int64)
+    cl = np.zeros(cap, dtype=np.int32)
+    log = np.zeros(max(cap * 2 * npair, 1), dtype=np.int64)
+    st = np.zeros(1, dtype=np.uint32)
+    cc = cfg.c()
+    k = lib().orc_cell_adaptive_trace(C.byref(cc), _ptr(xi), _ptr(v),
+                                      _ptr(attrs if cfg.n_attr else None), n, c, step_index, cap,
+                                      _ptr(dl), _ptr(ds), _ptr(nl), _ptr(cl), _ptr(log), _ptr(st))
+    subs = []
+    for i in range(k):
+        subs.append({"dt_left": float(dl[i]), "dt_sub": float(ds[i]), "n_live": int(nl[i]),
+                     "clamped": bool(cl[i]),
+                     "log": log[i * 2 * npair:(i + 1) * 2 * npair].reshape(-1, 2).copy()})
+    return subs, int(st[0])
 
 
 def moments(cfg: OracleConfig, xi, v, attrs, cell_off, vol_edges=None):

@@ -344,10 +344,37 @@ static double cell_pmax(const orc_cfg* cfg, const int64_t* xi, const double* v, 
  * that length clamped to 1.  After max_substeps substeps the remainder is
  * done in one unclamped substep and the SUBSTEP_CAP status bit is raised.
  */
+/*
+ * Optional record of every substep of one cell (test hook): for substep k,
+ * dt_left[k] and dt_sub[k] (seconds), n_live[k], clamped[k] (1 if p was
+ * clamped to 1, 0 for the unclamped remainder after the substep cap) and the
+ * pair log of that substep at log + k * 2 floor(n_slots / 2).
+ */
+typedef struct {
+  int32_t cap;
+  int32_t count;
+  double* dt_left;
+  double* dt_sub;
+  int64_t* n_live;
+  int32_t* clamped;
+  int64_t* log;
+} orc_trace;
+
+static int64_t* trace_slot(orc_trace* tr, int64_t n_slots, double dt_left, double dt_sub,
+                           int64_t n, int32_t clamped) {
+  if (!tr || tr->count >= tr->cap) return NULL;
+  int32_t k = tr->count++;
+  tr->dt_left[k] = dt_left;
+  tr->dt_sub[k] = dt_sub;
+  tr->n_live[k] = n;
+  tr->clamped[k] = clamped;
+  return tr->log + (int64_t)k * 2 * (n_slots / 2);
+}
+
 static int32_t cell_adaptive(const orc_cfg* cfg, int64_t* xi, double* v, double* attrs,
                              int64_t off, int64_t n_slots, int32_t c, uint32_t s,
                              keyed_slot* scratch, int64_t* order, int64_t* log, cell_tally* tally,
-                             uint32_t* status) {
+                             uint32_t* status, orc_trace* tr) {
   double dt_left = cfg->dt;
   uint32_t u = 0;
   int64_t n_live0 = -1;
@@ -358,8 +385,11 @@ static int32_t cell_adaptive(const orc_cfg* cfg, int64_t* xi, double* v, double*
     double pmax = cell_pmax(cfg, xi, v, off, order, n, dt_left / cfg->dv);
     double dt_sub = (pmax <= 1.0) ? dt_left : dt_left / pmax;
     cell_tally t = {0, 0, 0};
+    int64_t* tlog = trace_slot(tr, n_slots, dt_left, dt_sub, n, 1);
     cell_substep(cfg, xi, v, attrs, off, n_slots, c, s, u, dt_sub / cfg->dv, 1, scratch, order,
                  log, &t, status);
+    if (tlog && log)
+      for (int64_t i = 0; i < 2 * (n_slots / 2); ++i) tlog[i] = log[i];
     tally->n_colliding += t.n_colliding;
     dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
     u += 1;
@@ -368,8 +398,14 @@ static int32_t cell_adaptive(const orc_cfg* cfg, int64_t* xi, double* v, double*
     /* cap reached with time left: one unclamped substep for the remainder */
     *status |= ORC_ST_SUBSTEP_CAP;
     cell_tally t = {0, 0, 0};
+    int64_t* tlog = trace_slot(tr, n_slots, dt_left, dt_left, -1, 0);
     cell_substep(cfg, xi, v, attrs, off, n_slots, c, s, u, dt_left / cfg->dv, 0, scratch, order,
                  log, &t, status);
+    if (tlog) {
+      tr->n_live[tr->count - 1] = t.n_live;
+      if (log)
+        for (int64_t i = 0; i < 2 * (n_slots / 2); ++i) tlog[i] = log[i];
+    }
     tally->n_colliding += t.n_colliding;
     u += 1;
   }
@@ -425,7 +461,7 @@ uint32_t orc_step(const orc_cfg* cfg, int64_t* xi, double* v, double* attrs,
       int32_t nsub = 1;
       if (cfg->adaptive) {
         nsub = cell_adaptive(cfg, xi, v, attrs, off, ns, (int32_t)c, step, scratch, order, log, &t,
-                             &status);
+                             &status, NULL);
       } else {
         cell_substep(cfg, xi, v, attrs, off, ns, (int32_t)c, step, 0, q, 0, scratch, order, log, &t,
                      &status);
@@ -446,6 +482,31 @@ uint32_t orc_step(const orc_cfg* cfg, int64_t* xi, double* v, double* attrs,
   }
   free(pair_base);
   return status;
+}
+
+/*
+ * Test hook: one adaptive outer step of one cell (slots [0, n_slots) of the
+ * given arrays, cell index c, step s), recording every substep in the trace
+ * arrays (capacity cap substeps; the log holds cap x 2 floor(n_slots / 2)
+ * int64).  attrs: [n_attr][n_slots] with cfg->n_slots == n_slots.  Returns
+ * the number of substeps recorded; *status_out receives the status bits.
+ */
+int32_t orc_cell_adaptive_trace(const orc_cfg* cfg, int64_t* xi, double* v, double* attrs,
+                                int64_t n_slots, int32_t c, uint32_t s, int32_t cap,
+                                double* dt_left, double* dt_sub, int64_t* n_live,
+                                int32_t* clamped, int64_t* log, uint32_t* status_out) {
+  keyed_slot* scratch = (keyed_slot*)malloc(sizeof(keyed_slot) * (size_t)(n_slots > 0 ? n_slots : 1));
+  int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_slots > 0 ? n_slots : 1));
+  int64_t* one = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * (n_slots / 2) + 1));
+  orc_trace tr = {cap, 0, dt_left, dt_sub, n_live, clamped, log};
+  cell_tally t = {0, 0, 0};
+  uint32_t status = 0;
+  cell_adaptive(cfg, xi, v, attrs, 0, n_slots, c, s, scratch, order, one, &t, &status, &tr);
+  free(scratch);
+  free(order);
+  free(one);
+  if (status_out) *status_out = status;
+  return tr.count;
 }
 
 /* ------------------------------------------------------------------ */
