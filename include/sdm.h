@@ -48,7 +48,18 @@
  * Part of a step may run on the library's second stream, which waits for
  * `stream` (an event) and is joined back into it before the call returns, so
  * work enqueued on `stream` afterwards sees the step complete.  One handle
- * must not be stepped on two streams at once.
+ * must not be stepped on two streams at once: a step call (alone or in a
+ * batch) on another stream than the one its last steps were enqueued on,
+ * while those still run, returns SDM_EAGAIN and enqueues nothing.
+ *
+ * Synchronisation.  No call synchronises the whole device.  Calls that set
+ * up launch tables (sdm_init, sdm_batch_create, sdm_set_tuning, sdm_rebind,
+ * sdm_autotune) synchronise their `stream`; sdm_status_word and sdm_stats
+ * synchronise `stream` to read back.  Calls without a stream argument
+ * (sdm_debug_gamma_sink, sdm_batch_workspace_bytes,
+ * sdm_autotune_scratch_bytes) are host-only, except right after a
+ * device-side sdm_rebind, when they first copy the new offsets to the host
+ * with a blocking copy.
  */
 #ifndef SDM_H
 #define SDM_H
@@ -124,8 +135,10 @@ size_t sdm_workspace_bytes(const sdm_config* cfg, const int64_t* host_cell_off);
  * Create a simulation over caller-owned device state (see "Memory and
  * ownership").  attrs may be NULL when n_attr = 0.  workspace: device memory
  * of at least sdm_workspace_bytes bytes, 256-byte aligned.  Copies cell_off
- * to the host, validates cfg and the state (one kernel, then a stream
- * synchronisation), and plans the launches.  The step counter starts at 0.
+ * to the host, validates cfg, plans the launches and uploads the tables,
+ * and validates the state (one kernel), all ordered on `stream`, which it
+ * synchronises (twice; work on other streams keeps running).  The step
+ * counter starts at 0.
  * Returns SDM_EINVAL for a bad cfg/state (also: adaptive mode with a cell of
  * more than 16384 slots), SDM_ENOMEM if the workspace is too small.
  */
@@ -133,7 +146,8 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
                     const int64_t* cell_off, void* workspace, size_t workspace_bytes,
                     void* stream);
 
-/* Advance n_steps >= 0 outer steps (enqueue only). Steps beyond the step limit are skipped. */
+/* Advance n_steps >= 0 outer steps (enqueue only). Steps beyond the step limit are skipped.
+ * SDM_EAGAIN: the simulation's last steps were enqueued on another stream and still run. */
 sdm_status sdm_coalescence_step(sdm_sim* s, int32_t n_steps, void* stream);
 
 /*
@@ -194,13 +208,16 @@ sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_bytes, int32_t
  * Batches: simulations stepped together by shared launches (one launch per
  * step covers every member's cells).  Members keep their own state, seed,
  * kernel, counters and status.  workspace: device, >= sdm_batch_workspace_bytes.
- * Members must stay alive while the batch exists.
+ * Members must stay alive while the batch exists.  sdm_batch_create builds the
+ * launch tables on the host, uploads them on `stream` and synchronises `stream`.
  */
 size_t sdm_batch_workspace_bytes(sdm_sim* const* sims, int32_t n);
 sdm_status sdm_batch_create(sdm_batch** out, sdm_sim* const* sims, int32_t n, void* workspace,
                             size_t workspace_bytes, void* stream);
 /* Advance every member n_steps (each member honours its own step limit).
- * SDM_ESTATE if a member was re-pointed by sdm_rebind since the batch was made. */
+ * SDM_ESTATE if a member was re-pointed by sdm_rebind since the batch was made.
+ * SDM_EAGAIN (nothing enqueued) if a member's last steps were enqueued on another
+ * stream (alone or in another batch) and still run. */
 sdm_status sdm_batch_step(sdm_batch* b, int32_t n_steps, void* stream);
 void sdm_batch_free(sdm_batch* b);
 
@@ -216,7 +233,9 @@ const char* sdm_strerror(sdm_status st);
  * device and the call synchronises `stream` once to read back two words;
  * if a cell outgrew its size class, slots landed in a cell that had none, or
  * the offsets are not a valid layout, it falls back to the host re-plan:
- * cell_off is copied to the host and validated like in sdm_init.  Returns
+ * cell_off is copied to the host and validated like in sdm_init.  If a HIP
+ * call fails on the way, the old layout is re-planned (SDM_EDEVICE); if that
+ * fails too, later step calls return SDM_ESTATE.  Returns
  * SDM_EINVAL for an invalid layout (the handle keeps its old one), SDM_ENOMEM
  * if the new layout needs more workspace than the handle was given (size it
  * with sdm_workspace_bytes(cfg, NULL) to allow any layout).  A batch

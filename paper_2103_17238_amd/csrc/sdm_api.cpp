@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -60,6 +61,21 @@ bool tuning_ok(const sdm_tuning& t) {
 
 struct Plan;
 
+// The last stream a simulation's steps were enqueued on, and an event
+// recorded there after them.  A plan records one event per step call and
+// every member points at it, so the check in plan_step costs nothing for
+// members stepped on the same stream.
+struct Busy {
+  hipEvent_t ev = nullptr;
+  hipStream_t st = nullptr;
+  Busy() = default;
+  Busy(const Busy&) = delete;
+  Busy& operator=(const Busy&) = delete;
+  ~Busy() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
 struct sdm_sim {
   sdm_config cfg{};
   int64_t* xi = nullptr;
@@ -82,17 +98,21 @@ struct sdm_sim {
   int64_t* d_pair_base = nullptr;
   unsigned long long* d_rebind = nullptr;  // two result words of the device-side rebind
   uint32_t layout_gen = 0;                 // bumped by every sdm_rebind
+  bool broken = false;  // a failed re-plan left the launch tables unusable
+  std::shared_ptr<Busy> last;  // where the last step of this simulation was enqueued
   Plan* plan = nullptr;
 };
 
 static sdm_status rebind_host(sdm_sim* s, int64_t* xi, double* v, double* attrs,
                               const int64_t* cell_off, hipStream_t st);
 
-// Refreshes the host copy of the offsets after device-side rebinds.
+// Refreshes the host copy of the offsets after device-side rebinds.  The
+// device offsets are final once sdm_rebind returned (it synchronised the
+// stream that wrote them), so a blocking copy suffices; no device-wide
+// synchronisation.
 static bool fresh_offsets(const sdm_sim* s) {
   if (!s->off_stale) return true;
-  if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(s->off.data(), s->cell_off, sizeof(int64_t) * s->off.size(),
+  if (hipMemcpy(s->off.data(), s->cell_off, sizeof(int64_t) * s->off.size(),
                 hipMemcpyDeviceToHost) != hipSuccess) {
     (void)hipGetLastError();
     return false;
@@ -262,6 +282,7 @@ struct Plan {
   uint32_t counter = 0;       // launch step of the next step
   uint32_t flip = 0;          // steps launched since the tables were built
   sdm::SideStream side;       // created at the first step
+  std::shared_ptr<Busy> busy;  // event recorded after each step call, created at the first
   Plan() = default;
   Plan(const Plan&) = delete;
   Plan& operator=(const Plan&) = delete;
@@ -306,10 +327,11 @@ static SimDesc make_desc(const sdm_sim* s, uint32_t delta) {
     }                                     \
   } while (0)
 
+// stream-ordered upload; src must stay alive until `st` is synchronised
 template <typename T>
-static hipError_t upload(T* dst, const std::vector<T>& src) {
+static hipError_t upload(T* dst, const std::vector<T>& src, hipStream_t st) {
   if (src.empty()) return hipSuccess;
-  return hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+  return hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, st);
 }
 
 // LDS one workgroup may use on the current device
@@ -323,8 +345,12 @@ static size_t lds_block_limit() {
   return (size_t)std::max(a, b);
 }
 
-// (Re)build the plan tables for its members and upload them; syncs `st` first.
-static sdm_status plan_setup(Plan* p, hipStream_t st) {
+// (Re)build the plan tables for its members and upload them on `st`.  Syncs
+// `st` before (the old tables may be in use) and, with sync_end, after (the
+// host tables then need not outlive the call's caller; sdm_init instead
+// covers the uploads with its own later synchronisation).  No device-wide
+// synchronisation: work on other streams keeps running.
+static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   for (auto* m : p->members)
     if (!fresh_offsets(m)) return SDM_EDEVICE;
   p->T = Tables();
@@ -369,28 +395,30 @@ static sdm_status plan_setup(Plan* p, hipStream_t st) {
   d.tmp = reinterpret_cast<unsigned long long*>(w + L.tmp);
   d.ord = reinterpret_cast<uint32_t*>(w + L.ord);
 
+  // the old tables may still be read by steps enqueued on `st`
   HIP_TRY(hipStreamSynchronize(st));
   p->desc.clear();
   for (auto* s : p->members) p->desc.push_back(make_desc(s, s->step - p->counter));
-  HIP_TRY(upload(const_cast<SimDesc*>(d.desc), p->desc));
+  HIP_TRY(upload(const_cast<SimDesc*>(d.desc), p->desc, st));
   for (int k = 0; k < sdm::kNumClasses; ++k) {
-    HIP_TRY(upload(d.wave_tasks[k], p->T.wave[k]));
+    HIP_TRY(upload(d.wave_tasks[k], p->T.wave[k], st));
     const size_t na = p->T.wave[k].size() - (size_t)p->T.n_plain[k];
     if (na > 0)
-      HIP_TRY(hipMemcpy(d.wave_alt[k], p->T.wave[k].data() + p->T.n_plain[k],
-                        sizeof(sdm::CellTask) * na, hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpyAsync(d.wave_alt[k], p->T.wave[k].data() + p->T.n_plain[k],
+                             sizeof(sdm::CellTask) * na, hipMemcpyHostToDevice, st));
     p->flip = 0;
   }
   for (int k = 0; k < sdm::kNumMid; ++k)
-    HIP_TRY(upload(const_cast<sdm::CellTask*>(d.mid_tasks[k]), p->T.mid[k]));
-  HIP_TRY(upload(const_cast<BigTask*>(d.big), p->T.big));
-  HIP_TRY(upload(const_cast<BigChunk*>(d.chunks), p->T.chunks));
-  HIP_TRY(upload(const_cast<BigBucket*>(d.buckets), p->T.buckets));
-  HIP_TRY(upload(const_cast<BigPairBlock*>(d.pblocks), p->T.pblocks));
+    HIP_TRY(upload(const_cast<sdm::CellTask*>(d.mid_tasks[k]), p->T.mid[k], st));
+  HIP_TRY(upload(const_cast<BigTask*>(d.big), p->T.big, st));
+  HIP_TRY(upload(const_cast<BigChunk*>(d.chunks), p->T.chunks, st));
+  HIP_TRY(upload(const_cast<BigBucket*>(d.buckets), p->T.buckets, st));
+  HIP_TRY(upload(const_cast<BigPairBlock*>(d.pblocks), p->T.pblocks, st));
   if (p->T.bucket_total > 0)
-    HIP_TRY(hipMemset(d.bucket_cnt, 0, sizeof(uint32_t) * p->T.bucket_total));
-  if (!p->T.big.empty()) HIP_TRY(hipMemset(d.task_live, 0, sizeof(uint32_t) * p->T.big.size()));
-  HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemsetAsync(d.bucket_cnt, 0, sizeof(uint32_t) * p->T.bucket_total, st));
+  if (!p->T.big.empty())
+    HIP_TRY(hipMemsetAsync(d.task_live, 0, sizeof(uint32_t) * p->T.big.size(), st));
+  if (sync_end) HIP_TRY(hipStreamSynchronize(st));
   return SDM_OK;
 }
 
@@ -406,12 +434,28 @@ static sdm_status plan_refresh(Plan* p, hipStream_t st) {
   }
   if (!changed) return SDM_OK;
   HIP_TRY(hipStreamSynchronize(st));
-  HIP_TRY(upload(const_cast<SimDesc*>(p->dev.desc), p->desc));
+  HIP_TRY(upload(const_cast<SimDesc*>(p->dev.desc), p->desc, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return SDM_OK;
 }
 
 static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
   if (n_steps < 0) return SDM_EINVAL;
+  for (auto* m : p->members)
+    if (m->broken) return SDM_ESTATE;
+  // a member whose last steps were enqueued on another stream and still run
+  for (auto* m : p->members)
+    if (m->last && m->last->st != st) {
+      const hipError_t q = hipEventQuery(m->last->ev);
+      if (q == hipErrorNotReady) {
+        (void)hipGetLastError();
+        return SDM_EAGAIN;
+      }
+      if (q != hipSuccess) {
+        (void)hipGetLastError();
+        return SDM_EDEVICE;
+      }
+    }
   if (n_steps == 0) return SDM_OK;
   sdm_status r = plan_refresh(p, st);
   if (r != SDM_OK) return r;
@@ -440,6 +484,22 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
   for (auto* s : p->members) {
     const int64_t left = s->step < s->limit ? (int64_t)(s->limit - s->step) : 0;
     s->step += (uint32_t)std::min<int64_t>(left, n_steps);
+  }
+  if (active > 0) {  // members are busy on `st` until this event
+    if (!p->busy) {
+      p->busy = std::make_shared<Busy>();
+      if (hipEventCreateWithFlags(&p->busy->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        p->busy.reset();
+        return SDM_EDEVICE;
+      }
+    }
+    if (hipEventRecord(p->busy->ev, st) != hipSuccess) {
+      (void)hipGetLastError();
+      return SDM_EDEVICE;
+    }
+    p->busy->st = st;
+    for (auto* s : p->members) s->last = p->busy;
   }
   // keep descriptors consistent: members that hit their limit get re-synced lazily
   return SDM_OK;
@@ -545,9 +605,9 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
   s->attrs = cfg->n_attr > 0 ? attrs : nullptr;
   s->cell_off = cell_off;
   s->off.resize((size_t)cfg->n_cells + 1);
-  if (hipStreamSynchronize(st) != hipSuccess ||
-      hipMemcpy(s->off.data(), cell_off, sizeof(int64_t) * s->off.size(),
-                hipMemcpyDeviceToHost) != hipSuccess) {
+  if (hipMemcpyAsync(s->off.data(), cell_off, sizeof(int64_t) * s->off.size(),
+                     hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
     (void)hipGetLastError();
     delete s;
     return SDM_EDEVICE;
@@ -580,27 +640,6 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
   s->d_pair_base = reinterpret_cast<int64_t*>(w);
   w += align_up(sizeof(int64_t) * ((size_t)cfg->n_cells + 1));
 
-  std::vector<int64_t> pb((size_t)cfg->n_cells + 1, 0);
-  for (int c = 0; c < cfg->n_cells; ++c) pb[c + 1] = pb[c] + (s->off[c + 1] - s->off[c]) / 2;
-  bool ok = hipMemset(s->d_status, 0, sizeof(uint32_t)) == hipSuccess &&
-            hipMemset(s->d_stats, 0,
-                      sizeof(unsigned long long) * sdm::kStatSlots * sdm::kStatFields) ==
-                hipSuccess &&
-            hipMemcpy(s->d_pair_base, pb.data(), sizeof(int64_t) * pb.size(),
-                      hipMemcpyHostToDevice) == hipSuccess;
-  ok = ok && sdm::launch_validate(xi, v, cfg->n_slots, s->d_status, st) == hipSuccess;
-  uint32_t flags = 0;
-  ok = ok && hipStreamSynchronize(st) == hipSuccess &&
-       hipMemcpy(&flags, s->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess;
-  if (!ok) {
-    (void)hipGetLastError();
-    delete s;
-    return SDM_EDEVICE;
-  }
-  if (flags & sdm::kFlagInvalid) {
-    delete s;
-    return SDM_EINVAL;
-  }
   s->plan = new (std::nothrow) Plan();
   if (!s->plan) {
     delete s;
@@ -610,11 +649,35 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
   s->plan->ws = w;
   s->plan->ws_bytes = workspace_bytes - (size_t)(w - static_cast<char*>(workspace));
   s->plan->tuning = s->tuning;
-  const sdm_status r = plan_setup(s->plan, st);
-  if (r != SDM_OK) {
+  // Everything below is ordered on `st` and covered by one synchronisation
+  // of `st` (no device-wide one): counters, pair bases, the plan's tables,
+  // the validation kernel and the read-back of its flag.
+  std::vector<int64_t> pb((size_t)cfg->n_cells + 1, 0);
+  for (int c = 0; c < cfg->n_cells; ++c) pb[c + 1] = pb[c] + (s->off[c + 1] - s->off[c]) / 2;
+  uint32_t flags = 0;
+  bool ok = hipMemsetAsync(s->d_status, 0, sizeof(uint32_t), st) == hipSuccess &&
+            hipMemsetAsync(s->d_stats, 0,
+                           sizeof(unsigned long long) * sdm::kStatSlots * sdm::kStatFields,
+                           st) == hipSuccess &&
+            hipMemcpyAsync(s->d_pair_base, pb.data(), sizeof(int64_t) * pb.size(),
+                           hipMemcpyHostToDevice, st) == hipSuccess;
+  const sdm_status r = ok ? plan_setup(s->plan, st, false) : SDM_EDEVICE;
+  ok = ok && r == SDM_OK &&
+       sdm::launch_validate(xi, v, cfg->n_slots, s->d_status, st) == hipSuccess &&
+       hipMemcpyAsync(&flags, s->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, st) ==
+           hipSuccess;
+  // pb, flags and the plan's host tables are alive until here
+  const bool synced = hipStreamSynchronize(st) == hipSuccess;
+  if (!ok || !synced) {
+    (void)hipGetLastError();
     delete s->plan;
     delete s;
-    return r;
+    return r != SDM_OK ? r : SDM_EDEVICE;
+  }
+  if (flags & sdm::kFlagInvalid) {
+    delete s->plan;
+    delete s;
+    return SDM_EINVAL;
   }
   *out = s;
   return SDM_OK;
@@ -659,9 +722,9 @@ sdm_status sdm_stats(sdm_sim* s, uint64_t out[4], void* stream) {
   if (!s || !out) return SDM_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   std::vector<unsigned long long> h((size_t)sdm::kStatSlots * sdm::kStatFields);
+  HIP_TRY(hipMemcpyAsync(h.data(), s->d_stats, sizeof(unsigned long long) * h.size(),
+                         hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  HIP_TRY(hipMemcpy(h.data(), s->d_stats, sizeof(unsigned long long) * h.size(),
-                    hipMemcpyDeviceToHost));
   for (int f = 0; f < 4; ++f) out[f] = 0;
   for (int i = 0; i < sdm::kStatSlots; ++i)
     for (int f = 0; f < sdm::kStatFields; ++f) out[f] += h[(size_t)i * sdm::kStatFields + f];
@@ -746,9 +809,13 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
             hipSuccess ||
         hipMemcpyAsync(const_cast<SimDesc*>(pd.desc), p->desc.data(), sizeof(SimDesc),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess ||
-        hipMemcpy(w, s->d_rebind, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) {
+        hipMemcpyAsync(w, s->d_rebind, sizeof(w), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      // the tables may be half rewritten for the new buffers while the
+      // handle still names the old ones: re-plan the old layout, or refuse
+      // further steps if that fails too
       (void)hipGetLastError();
+      if (plan_setup(s->plan, st) != SDM_OK) s->broken = true;
       return SDM_EDEVICE;
     }
     if (w[0] == 0 && w[1] == (unsigned long long)cfg.n_slots) {
@@ -767,7 +834,10 @@ sdm_status sdm_rebind(sdm_sim* s, int64_t* xi, double* v, double* attrs, const i
   const sdm_status r = rebind_host(s, xi, v, attrs, cell_off, st);
   if (r != SDM_OK && only_wave) {
     const sdm_status r2 = plan_setup(s->plan, st);
-    if (r2 != SDM_OK) return r2;
+    if (r2 != SDM_OK) {
+      s->broken = true;
+      return r2;
+    }
   }
   return r;
 }
@@ -776,9 +846,9 @@ static sdm_status rebind_host(sdm_sim* s, int64_t* xi, double* v, double* attrs,
                               const int64_t* cell_off, hipStream_t st) {
   const sdm_config& cfg = s->cfg;
   std::vector<int64_t> off((size_t)cfg.n_cells + 1);
-  if (hipStreamSynchronize(st) != hipSuccess ||
-      hipMemcpy(off.data(), cell_off, sizeof(int64_t) * off.size(), hipMemcpyDeviceToHost) !=
-          hipSuccess) {
+  if (hipMemcpyAsync(off.data(), cell_off, sizeof(int64_t) * off.size(), hipMemcpyDeviceToHost,
+                     st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
     (void)hipGetLastError();
     return SDM_EDEVICE;
   }
@@ -790,8 +860,9 @@ static sdm_status rebind_host(sdm_sim* s, int64_t* xi, double* v, double* attrs,
     return SDM_ENOMEM;
   std::vector<int64_t> pb((size_t)cfg.n_cells + 1, 0);
   for (int c = 0; c < cfg.n_cells; ++c) pb[c + 1] = pb[c] + (off[c + 1] - off[c]) / 2;
-  if (hipMemcpy(s->d_pair_base, pb.data(), sizeof(int64_t) * pb.size(), hipMemcpyHostToDevice) !=
-      hipSuccess) {
+  if (hipMemcpyAsync(s->d_pair_base, pb.data(), sizeof(int64_t) * pb.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
     (void)hipGetLastError();
     return SDM_EDEVICE;
   }
