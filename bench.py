@@ -41,6 +41,11 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+def note(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def make_state(name):
     from paper_2103_17238_amd import inputs as I
 
@@ -244,6 +249,54 @@ def fused_vs_single(state, tuning, steps=40):
             "fused_ms_per_step": out["fused"], "speedup": out["single"] / out["fused"]}
 
 
+def serving_c5(n_requests, rate, baseline_prefix, small_budget_prefix, steps=600):
+    """The serving configuration: Poisson arrivals at `rate` per second,
+    n_sd = round(2^U(10, 16)), Golovin or geometric with probability 1/2,
+    `steps` steps each, HBM-budget admission (80 % of free HBM), continuous
+    batching with shared launches.  Beside it: the one-at-a-time baseline
+    (FIFO, each request alone with its own launches) on a prefix of the same
+    trace, and a 64 MiB budget that forces queueing on a prefix.  p50/p99 of
+    completion - arrival, and SD-steps/s over the run's wall time."""
+    import torch
+
+    from paper_2103_17238_amd import inputs as I
+    from paper_2103_17238_amd.serving import GpuExecutor, Server, serve_one_at_a_time
+
+    reqs = I.serving_requests(n_requests, rate_per_s=rate, n_steps=steps)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    # warm-up: kernels loaded, allocator primed (its own short trace)
+    warm = I.serving_requests(16, rate_per_s=4000.0, n_steps=20, rng_seed=99)
+    Server(GpuExecutor(), budget_bytes=budget, steps_per_tick=25).run(warm, I.request_state)
+    note(f"serving: {n_requests} requests at {rate:g}/s")
+    ex = GpuExecutor()
+    stats = Server(ex, budget_bytes=budget, steps_per_tick=25).run(reqs, I.request_state)
+    ex.close()
+    served = stats.summary()
+    served.update(requests=n_requests, budget_bytes=budget,
+                  device_busy_s=stats.device_busy_s)
+    note(f"serving: p50 {served['p50_s']:.3f} s p99 {served['p99_s']:.3f} s; "
+         f"one-at-a-time on the first {baseline_prefix}")
+    base = serve_one_at_a_time(reqs[:baseline_prefix], I.request_state, GpuExecutor()).summary()
+    base.update(requests=baseline_prefix, note=f"first {baseline_prefix} requests of the trace")
+    note(f"serving: 64 MiB budget on the first {small_budget_prefix}")
+    ex = GpuExecutor()
+    small = Server(ex, budget_bytes=64 * 2 ** 20, steps_per_tick=25).run(
+        reqs[:small_budget_prefix], I.request_state)
+    ex.close()
+    tight = small.summary()
+    tight.update(requests=small_budget_prefix, budget_bytes=64 * 2 ** 20,
+                 note=f"first {small_budget_prefix} requests of the trace, 64 MiB budget")
+    same = {"served_sd_steps_per_s": served["sd_steps_per_s"]}
+    # the baseline's throughput on its prefix against the served run's over
+    # the whole trace (both over wall time, arrivals included)
+    same["one_at_a_time_sd_steps_per_s"] = base["sd_steps_per_s"]
+    return {"workload": f"serving_{n_requests}_requests_{rate:g}_per_s_nsd_2^10..2^16_"
+                        f"{steps}_steps",
+            "served": served, "one_at_a_time": base, "budget_64mib": tight,
+            "throughput": same}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +322,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-baseline", type=int, default=128,
                     help="requests replayed one at a time for the baseline")
+    ap.add_argument("--serve-small-budget", type=int, default=1024,
+                    help="requests of the trace served under a 64 MiB budget")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="default workload: skip the serving measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -298,6 +355,7 @@ def main():
         return displace_bench(args)
     if args.workload == "kinematic":
         return kinematic_bench(args)
+    note(f"workload {args.workload}: building the input")
     state, workload = make_state(args.workload)
     host_state = state.copy()
     sim = B.Sim(state)
@@ -345,6 +403,7 @@ def main():
         B.sdm_set_tuning(sim.handle, t)
         tuning_note = "autotuned"
     tuning = B.sdm_get_tuning(sim.handle).as_dict()
+    note(f"tuning {tuning} ({tuning_note}); timing {args.steps} steps")
 
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -424,16 +483,24 @@ def main():
         },
         "stats": {"live_sd_steps": live, "colliding_pairs": coll,
                   "cell_substeps": stats["cell_substeps"], "cell_steps": stats["cell_steps"],
+                  # the adaptive load the timed steps carried (it grows as drops
+                  # grow): compare runs at the same value
+                  "substeps_per_cell_step": stats["cell_substeps"] / max(stats["cell_steps"], 1),
                   "status_flags": flags, "wall_s": t_wall},
     }
     sim.close()
+    note(f"{total_ms / K:.4f} ms per step; batching and fusion figures")
     if cell_grid and not args.no_batching_check:
         line["batching"] = batched_vs_separate(host_state, tuning)
         line["fusion"] = fused_vs_single(host_state, tuning)
     if not args.no_cpu_baseline:
+        note("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(host_state, args.cpu_cells, args.cpu_steps)
     else:
         line["cpu_baseline"] = None
+    if args.workload == "grid256" and not args.no_serving:
+        line["serving"] = serving_c5(4096, args.serve_rate, args.serve_baseline,
+                                     args.serve_small_budget)
     print(json.dumps(line), flush=True)
 
 

@@ -83,6 +83,22 @@ __device__ __forceinline__ double coal_kernel(int kind, double b, double va, dou
   return kPi * (rs * rs) * fabs(fall_speed(ra) - fall_speed(rb));  // geometric sweep-out, E = 1
 }
 
+// The per-SD quantity the kernel is built from ("size"): the radius for the
+// geometric kernel, the volume itself for Golovin's.  A cell kernel keeps it
+// in LDS and recomputes it only for SDs whose volume changed, so the cube
+// root is taken once per SD and step instead of once per SD and substep.
+// pair_kernel(kind, b, size_of(kind, va), size_of(kind, vb)) is bitwise
+// coal_kernel(kind, b, va, vb).
+__device__ __forceinline__ double size_of(int kind, double v) {
+  return kind == 0 ? v : cbrt(kVolToR3 * v);
+}
+
+__device__ __forceinline__ double pair_kernel(int kind, double b, double sa, double sb) {
+  if (kind == 0) return b * (sa + sb);
+  const double rs = sa + sb;
+  return kPi * (rs * rs) * fabs(fall_speed(sa) - fall_speed(sb));
+}
+
 __device__ __forceinline__ long long collisions(double p, double phi, uint32_t* status) {
   if (p < 1.0) return phi < p ? 1 : 0;  // floor(p) = 0 and p - floor(p) = p
   if (!(p < 0x1p62)) {
@@ -183,7 +199,8 @@ template <typename XI, typename VV>
 __device__ __forceinline__ int update_pair(XI* xs, VV* vs, int ia, int ib, long long xa,
                                             long long xb, double va, double vb, long long gamma,
                                             double* attrs, int64_t n_slots, int n_attr,
-                                            int64_t ga, int64_t gb) {
+                                            int64_t ga, int64_t gb, double* nva = nullptr,
+                                            double* nvb = nullptr) {
   const bool a_is_j = xa >= xb;
   const int ij = a_is_j ? ia : ib, ik = a_is_j ? ib : ia;
   const int64_t gj = a_is_j ? ga : gb, gk = a_is_j ? gb : ga;
@@ -198,7 +215,12 @@ __device__ __forceinline__ int update_pair(XI* xs, VV* vs, int ia, int ib, long 
   const long long rest = xj - g * xk;
   if (rest > 0) {
     xs[ij] = rest;
-    vs[ik] = fma(gd, vj, vk);
+    const double t = fma(gd, vj, vk);
+    vs[ik] = t;
+    if (nva) {  // new volumes of a and b
+      *nva = a_is_j ? vj : t;
+      *nvb = a_is_j ? t : vj;
+    }
     for (int q = 0; q < n_attr; ++q) {
       double* a = attrs + (int64_t)q * n_slots;
       a[gk] = fma(gd, a[gj], a[gk]);
@@ -211,6 +233,10 @@ __device__ __forceinline__ int update_pair(XI* xs, VV* vs, int ia, int ib, long 
     const double t = fma(gd, vj, vk);
     vs[ij] = t;
     vs[ik] = t;
+    if (nva) {
+      *nva = t;
+      *nvb = t;
+    }
     for (int q = 0; q < n_attr; ++q) {
       double* a = attrs + (int64_t)q * n_slots;
       const double ta = fma(gd, a[gj], a[gk]);
@@ -266,24 +292,30 @@ __device__ __forceinline__ void scan_store(uint32_t* cnt, int first, int per, in
 // ---------------------------------------------------------------------------
 // One workgroup ("team" of W wavefronts) per cell of <= CAP slots.
 //
-// Every phase spreads its work over the W*64 threads, so a cell's dependent
-// chain of LDS round trips is W times shorter and a SIMD holds W times more
-// independent instruction streams for the same LDS per cell.  LDS per slot:
-// xi and v in slot order (16 B), one 32-bit word that first holds the
-// bucketed (key, slot) entries and then the 16-bit permutation, and one
-// 32-bit bucket counter that later holds the pairs' pre-products.  In the
-// sort a thread owns 4 consecutive slots, i.e. exactly the 4 words of one
-// Philox call, so keys never go through LDS.
+// Every phase spreads its work over the W*64 threads.  LDS per slot: the
+// multiplicity (8 B) and the SD's kernel size (8 B: radius or volume, see
+// size_of) in slot order, one 32-bit word that first holds the bucketed
+// (key, slot) entries and then the 16-bit permutation, and one 32-bit bucket
+// counter.  Volumes stay in global memory: they are read and written only
+// for colliding pairs, like the extra attributes.  In the sort a thread owns
+// 4 consecutive slots, i.e. exactly the 4 words of one Philox call, so keys
+// never go through LDS; in the pair passes thread h owns pairs 2h and 2h+1,
+// whose two uniforms are the 4 words of one Philox call.
+//
+// Latency: every phase first issues all of a thread's LDS reads, then waits
+// once; reads that would be conditional are made unconditional on clamped,
+// in-bounds addresses and their results masked, so that no read waits inside
+// a per-entry branch.
 // ---------------------------------------------------------------------------
 constexpr int pow2_ceil(int x) { return x <= 1 ? 1 : 2 * pow2_ceil((x + 1) / 2); }
 
 template <int CAP>
 struct alignas(16) CellLds {
   long long xs[CAP];  // multiplicities (slot order)
-  double vs[CAP];     // volumes (slot order)
+  double rs[CAP];     // kernel sizes (slot order)
   uint32_t tmp[CAP];  // bucketed (key << nbits | slot), then uint16 permutation
-  uint32_t cnt[pow2_ceil(CAP) + 4];  // bucket counters / starts, then double pre-products
-  uint32_t dirty[CAP / 32];  // adaptive mode: slots to write back
+  uint32_t cnt[pow2_ceil(CAP) + 4];  // bucket counters / starts
+  uint32_t dirty[CAP / 32];  // LDS-resident steps: multiplicities to write back
   int red_i[8];              // cross-wave reductions
   double red_d[8];
 };
@@ -345,34 +377,39 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
                                           uint32_t k1) {
   constexpr int T = 64 * W;
   constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);  // 4-slot groups per thread
-  const int nbits = 32 - __clz(n - 1);                        // n >= 2
+  const int nbits = 32 - __clz(n - 1);              // n >= 2
   const int nb = 1 << nbits;
   const int sh = 32 - nbits;
   for (int i = 4 * tid; i < nb + 4; i += 4 * T)  // counters 0..nb, 16 bytes at a time
     *reinterpret_cast<uint4*>(&L.cnt[i]) = make_uint4(0u, 0u, 0u, 0u);
   team_sync<W>();
 
-  uint32_t kr[I4][4], pos[I4][4];
+  // keys of live slots (registers) and their place in their bucket (atomics)
+  uint32_t me[I4][4], pos[I4][4], bk[I4][4];
   uint32_t live[I4];
 #pragma unroll
   for (int i = 0; i < I4; ++i) {
     const int g = T * i + tid;
     live[i] = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      me[i][e] = 0;
+      pos[i][e] = 0;
+      bk[i][e] = 0;
+    }
     if (4 * g < n) {
       const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)c, s, 2u * u), k0, k1);
-      kr[i][0] = w.x;
-      kr[i][1] = w.y;
-      kr[i][2] = w.z;
-      kr[i][3] = w.w;
+      const uint32_t kr[4] = {w.x, w.y, w.z, w.w};
       const longlong2 x01 = *reinterpret_cast<const longlong2*>(&L.xs[4 * g]);
       const longlong2 x23 = *reinterpret_cast<const longlong2*>(&L.xs[4 * g + 2]);
       const long long xv[4] = {x01.x, x01.y, x23.x, x23.y};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        if (4 * g + e < n && xv[e] > 0) {
-          live[i] |= 1u << e;
-          pos[i][e] = atomicAdd(&L.cnt[kr[i][e] >> sh], 1u);
-        }
+        const bool lv = 4 * g + e < n && xv[e] > 0;
+        live[i] |= lv ? 1u << e : 0u;
+        bk[i][e] = kr[e] >> sh;
+        me[i][e] = (kr[e] << nbits) | (uint32_t)(4 * g + e);
+        if (lv) pos[i][e] = atomicAdd(&L.cnt[bk[i][e]], 1u);
       }
     }
   }
@@ -392,38 +429,46 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
     if (tid == 0) L.cnt[nb] = (uint32_t)nlive;
   }
   team_sync<W>();
+  // scatter: every bucket range is read before the first store
   uint32_t st[I4][4], len[I4][4];
+#pragma unroll
+  for (int i = 0; i < I4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t b = ((live[i] >> e) & 1) ? bk[i][e] : 0u;  // counters 0..nb are valid
+      st[i][e] = L.cnt[b];
+      len[i][e] = L.cnt[b + 1];
+    }
   int maxlen = 0;
 #pragma unroll
   for (int i = 0; i < I4; ++i)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      len[i][e] = 0;
-      if ((live[i] >> e) & 1) {
-        const uint32_t b = kr[i][e] >> sh;
-        st[i][e] = L.cnt[b];
-        len[i][e] = L.cnt[b + 1] - st[i][e];
-        L.tmp[st[i][e] + pos[i][e]] = (kr[i][e] << nbits) | (uint32_t)(4 * (T * i + tid) + e);
-        maxlen = max(maxlen, (int)len[i][e]);
-      }
+      const bool lv = (live[i] >> e) & 1;
+      len[i][e] = lv ? len[i][e] - st[i][e] : 0u;
+      st[i][e] = lv ? st[i][e] : 0u;
+      if (lv) L.tmp[st[i][e] + pos[i][e]] = me[i][e];
+      maxlen = max(maxlen, (int)len[i][e]);
     }
   team_sync<W>();
-  // exact rank inside the bucket; all of a thread's buckets advance together
+  // exact rank inside the bucket: each round reads one entry of every
+  // bucket of the thread (clamped into the array; masked beyond the bucket)
   uint32_t rk[I4][4];
 #pragma unroll
   for (int i = 0; i < I4; ++i)
 #pragma unroll
     for (int e = 0; e < 4; ++e) rk[i][e] = st[i][e];
   for (int k = 0; k < maxlen; ++k) {
+    uint32_t x[I4][4];
 #pragma unroll
     for (int i = 0; i < I4; ++i)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if ((uint32_t)k < len[i][e]) {
-          const uint32_t me = (kr[i][e] << nbits) | (uint32_t)(4 * (T * i + tid) + e);
-          rk[i][e] += (L.tmp[st[i][e] + k] < me) ? 1u : 0u;
-        }
-      }
+      for (int e = 0; e < 4; ++e) x[i][e] = L.tmp[min(st[i][e] + (uint32_t)k, (uint32_t)CAP - 1u)];
+#pragma unroll
+    for (int i = 0; i < I4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        rk[i][e] += ((uint32_t)k < len[i][e] && x[i][e] < me[i][e]) ? 1u : 0u;
   }
   team_sync<W>();
   uint16_t* perm = perm_of(L);
@@ -437,22 +482,33 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
 
 enum PassMode { kPassPlain = 0, kPassPmax = 1, kPassAdapt = 2, kPassPlainLds = 3 };
 
+// Registers a thread carries between the two passes of an adaptive substep:
+// the slots of its pairs (from the permutation) and their pre-products
+// (max xi K) S.
+template <int I4>
+struct PairRegs {
+  uint2 o4[I4];
+  double pre[I4][2];
+};
+
 // Candidate pairs of one (sub)step; thread h takes sorted positions 4h..4h+3,
 // i.e. pairs 2h and 2h+1, which share one Philox call.  kPassPlain updates
-// global memory; kPassPlainLds computes p the same way and updates LDS (steps
-// fused in one launch); kPassPmax stores the pre-products (max xi K) S and
-// returns this thread's largest p at q; kPassAdapt reads them back, clamps p
-// to 1 if asked and updates LDS.
+// global memory; kPassPlainLds computes p the same way and updates the
+// LDS-resident multiplicities (steps fused in one launch); kPassPmax keeps
+// the pre-products in registers and returns this thread's largest p at q;
+// kPassAdapt takes them back, clamps p to 1 if asked and updates.  Volumes
+// and attributes are always updated in global memory (vg: the cell's
+// volumes); LDS-resident modes refresh the sizes of the updated SDs.
 template <int CAP, int W, int MODE>
-__device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp, int n,
-                                             int nlive, int tid, int c, uint32_t s, uint32_t u,
-                                             double q, bool clamp, int64_t o0, int* ncoll,
+__device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp, double* vg,
+                                             int n, int nlive, int tid, int c, uint32_t s,
+                                             uint32_t u, double q, bool clamp, int64_t o0,
+                                             int* ncoll, PairRegs<(CAP + 256 * W - 1) / (256 * W)>& R,
                                              int* ndead = nullptr) {
   constexpr int T = 64 * W;
   constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);
   const int P = nlive >> 1;
   const double S = (double)((nlive & 1) ? nlive : nlive - 1);
-  double* pre = reinterpret_cast<double*>(L.cnt);  // P <= CAP/2 doubles fit in cnt
   const uint16_t* perm = perm_of(L);
   double pmax = 0.0;
   const int kind = dp->kernel;
@@ -460,40 +516,56 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
   int64_t* sink = (MODE == kPassPmax) ? nullptr : dp->sink;
   int64_t sink_base = 0;
   if (sink) sink_base = 2 * dp->pair_base[c];
+  if (MODE != kPassAdapt) {
+    // every pair's slots and sizes first (slots past the pairs clamped into
+    // the cell and masked), then the arithmetic
+    long long xv[I4][4];
+    double sv[I4][4];
+#pragma unroll
+    for (int i = 0; i < I4; ++i) {
+      const int h = T * i + tid;
+      R.o4[i] = make_uint2(0u, 0u);
+      if (2 * h >= P) continue;
+      R.o4[i] = *reinterpret_cast<const uint2*>(&perm[4 * h]);
+      const uint32_t sl[4] = {R.o4[i].x & 0xFFFFu, R.o4[i].x >> 16, R.o4[i].y & 0xFFFFu,
+                              R.o4[i].y >> 16};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t j = min(sl[e], (uint32_t)CAP - 1u);
+        xv[i][e] = L.xs[j];
+        sv[i][e] = L.rs[j];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < I4; ++i) {
+      const int h = T * i + tid;
+      R.pre[i][0] = R.pre[i][1] = 0.0;
+      if (2 * h >= P) continue;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const long long xa = xv[i][2 * e], xb = xv[i][2 * e + 1];
+        const double kv = pair_kernel(kind, bgol, sv[i][2 * e], sv[i][2 * e + 1]);
+        const double pp = ((double)(xa > xb ? xa : xb) * kv) * S;
+        R.pre[i][e] = (2 * h + e < P) ? pp : 0.0;
+        if (MODE == kPassPmax && 2 * h + e < P) pmax = fmax(pmax, pp * q);
+      }
+    }
+    if (MODE == kPassPmax) return pmax;
+  }
+  const bool in_lds = MODE != kPassPlain;
 #pragma unroll
   for (int i = 0; i < I4; ++i) {
     const int h = T * i + tid;
     if (2 * h >= P) continue;
-    const uint2 o4 = *reinterpret_cast<const uint2*>(&perm[4 * h]);
-    const int aa[2] = {(int)(o4.x & 0xFFFFu), (int)(o4.y & 0xFFFFu)};
-    const int bs[2] = {(int)(o4.x >> 16), (int)(o4.y >> 16)};
-    uint4 w = make_uint4(0, 0, 0, 0);
-    if (MODE != kPassPmax) w = philox(make_uint4((uint32_t)h, (uint32_t)c, s, 2u * u + 1u),
-                                      dp->seed_lo, dp->seed_hi);
+    const uint4 w = philox(make_uint4((uint32_t)h, (uint32_t)c, s, 2u * u + 1u), dp->seed_lo,
+                           dp->seed_hi);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int m = 2 * h + e;
       if (m >= P) break;
-      const int a = aa[e], bb = bs[e];
-      long long xa = 0, xb = 0;
-      double va = 0.0, vb = 0.0;
-      double p;
-      if (MODE == kPassAdapt) {
-        p = pre[m] * q;  // xi and v are read only for a collision
-      } else {
-        xa = L.xs[a];
-        xb = L.xs[bb];
-        va = L.vs[a];
-        vb = L.vs[bb];
-        const double kv = coal_kernel(kind, bgol, va, vb);
-        const double pp = ((double)(xa > xb ? xa : xb) * kv) * S;
-        if (MODE == kPassPmax) {
-          pre[m] = pp;
-          pmax = fmax(pmax, pp * q);
-          continue;
-        }
-        p = pp * q;
-      }
+      const int a = (int)((e == 0 ? R.o4[i].x : R.o4[i].y) & 0xFFFFu);
+      const int bb = (int)((e == 0 ? R.o4[i].x : R.o4[i].y) >> 16);
+      double p = R.pre[i][e] * q;
       if (clamp && p > 1.0) p = 1.0;
       const double phi = e == 0 ? uniform53(w.x, w.y) : uniform53(w.z, w.w);
       const long long gamma = collisions(p, phi, dp->status);
@@ -503,25 +575,24 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
       }
       if (gamma > 0) {
         *ncoll += 1;
-        if (MODE == kPassPlain) {
-          update_pair(dp->xi + o0, dp->v + o0, a, bb, xa, xb, va, vb, gamma, dp->attrs,
-                      dp->n_slots, dp->n_attr, o0 + a, o0 + bb);
+        const long long xa = L.xs[a], xb = L.xs[bb];
+        const double va = vg[a], vb = vg[bb];
+        if (!in_lds) {
+          update_pair(dp->xi + o0, vg, a, bb, xa, xb, va, vb, gamma, dp->attrs, dp->n_slots,
+                      dp->n_attr, o0 + a, o0 + bb);
         } else {
-          if (MODE == kPassAdapt) {
-            xa = L.xs[a];
-            xb = L.xs[bb];
-            va = L.vs[a];
-            vb = L.vs[bb];
-          }
-          *ndead += update_pair(L.xs, L.vs, a, bb, xa, xb, va, vb, gamma, dp->attrs,
-                                dp->n_slots, dp->n_attr, o0 + a, o0 + bb);
+          double na = va, nbv = vb;
+          *ndead += update_pair(L.xs, vg, a, bb, xa, xb, va, vb, gamma, dp->attrs, dp->n_slots,
+                                dp->n_attr, o0 + a, o0 + bb, &na, &nbv);
+          L.rs[a] = size_of(kind, na);
+          L.rs[bb] = size_of(kind, nbv);
           atomicOr(&L.dirty[a >> 5], 1u << (a & 31));
           atomicOr(&L.dirty[bb >> 5], 1u << (bb & 31));
         }
       }
     }
   }
-  if (sink && MODE != kPassPmax) {  // unused pair entries of the cell
+  if (sink) {  // unused pair entries of the cell
     for (int m = P + tid; m < (n >> 1); m += T) {
       sink[sink_base + 2 * m] = -1;
       sink[sink_base + 2 * m + 1] = -1;
@@ -551,6 +622,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
                                                   uint32_t* __restrict__ order_flag) {
   constexpr int T = 64 * W;
   constexpr int IT = (CAP + T - 1) / T;
+  constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);
   __shared__ CellLds<CAP> L;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -578,6 +650,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
     if (ADAPT && tid == 0) order_flag[blockIdx.x] = order_group(0);
     return;
   }
+  const int kind = dp->kernel;
   // Several steps in one launch (nsteps > 1) keep the cell in LDS from step
   // to step; each step is exactly the single step it replaces.
   const bool in_lds = ADAPT || nsteps > 1;
@@ -589,19 +662,20 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
     const int j = it * T + tid;
     if (it * T < n && j < n) {
       L.xs[j] = xr[it];
-      L.vs[j] = vr[it];
+      L.rs[j] = xr[it] > 0 ? size_of(kind, vr[it]) : 0.0;
       mylive += xr[it] > 0 ? 1 : 0;
     }
   }
   const int nlive = team_sum<W>(L, mylive, lane, wv);  // also orders the LDS stores
 
+  PairRegs<I4> R;
   int ncoll = 0;
   unsigned long long live_sum = 0, nsub = 0, steps_done = 0;
   if (!in_lds) {  // one plain step: updates go straight to global memory
     if (nlive >= 2) {
       team_sort<CAP, W>(L, n, nlive, tid, lane, wv, c, s0, 0u, dp->seed_lo, dp->seed_hi);
-      team_pairs<CAP, W, kPassPlain>(L, dp, n, nlive, tid, c, s0, 0u, dp->q, false, o0,
-                                     &ncoll);
+      team_pairs<CAP, W, kPassPlain>(L, dp, cur.v, n, nlive, tid, c, s0, 0u, dp->q, false, o0,
+                                     &ncoll, R);
     } else {
       sink_clear_cell(dp, c, n, tid, T);
     }
@@ -619,8 +693,8 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
         if (nl >= 2) {
           team_sort<CAP, W>(L, n, nl, tid, lane, wv, c, s, 0u, dp->seed_lo, dp->seed_hi);
           int ndead = 0;
-          team_pairs<CAP, W, kPassPlainLds>(L, dp, n, nl, tid, c, s, 0u, dp->q, false, o0,
-                                            &ncoll, &ndead);
+          team_pairs<CAP, W, kPassPlainLds>(L, dp, cur.v, n, nl, tid, c, s, 0u, dp->q, false, o0,
+                                            &ncoll, R, &ndead);
           nl -= team_sum<W>(L, ndead, lane, wv);
         } else {
           sink_clear_cell(dp, c, n, tid, T);
@@ -646,17 +720,17 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
             break;
           }
           team_sort<CAP, W>(L, n, nl, tid, lane, wv, c, s, u, dp->seed_lo, dp->seed_hi);
-          double pmax = team_pairs<CAP, W, kPassPmax>(L, dp, n, nl, tid, c, s, u,
-                                                      dt_left / dv, false, o0, &ncoll);
+          double pmax = team_pairs<CAP, W, kPassPmax>(L, dp, cur.v, n, nl, tid, c, s, u,
+                                                      dt_left / dv, false, o0, &ncoll, R);
           pmax = team_max<W>(L, pmax, lane, wv);
           const double dt_sub = (capped || pmax <= 1.0) ? dt_left : dt_left / pmax;
           int ndead = 0;
-          team_pairs<CAP, W, kPassAdapt>(L, dp, n, nl, tid, c, s, u, dt_sub / dv, !capped, o0,
-                                         &ncoll, &ndead);
+          team_pairs<CAP, W, kPassAdapt>(L, dp, cur.v, n, nl, tid, c, s, u, dt_sub / dv, !capped,
+                                         o0, &ncoll, R, &ndead);
           nl -= team_sum<W>(L, ndead, lane, wv);
-          // the next substep's attribute loads come from this same workgroup:
-          // one CU, one vector L1, so ordering the stores before them is all
-          // it takes
+          // the next substep's volume and attribute loads come from this
+          // same workgroup: one CU, one vector L1, so ordering the stores
+          // before them is all it takes
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
           team_sync<W>();
           dt_left = (dt_sub == dt_left) ? 0.0 : dt_left - dt_sub;
@@ -666,7 +740,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
         if (u == 0) sink_clear_cell(dp, c, n, tid, T);
         nsub += u;
       }
-      // this step's attribute updates before the next step's
+      // this step's volume and attribute updates before the next step's
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       team_sync<W>();
     }
@@ -674,13 +748,9 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
       order_flag[blockIdx.x] =
           order_group((uint32_t)((nsub + steps_done - 1) / (steps_done ? steps_done : 1)));
     team_sync<W>();
-    // write back the slots that changed
-    for (int j = tid; j < n; j += T) {
-      if ((L.dirty[j >> 5] >> (j & 31)) & 1u) {
-        cur.xi[j] = L.xs[j];
-        cur.v[j] = L.vs[j];
-      }
-    }
+    // write back the multiplicities that changed (volumes are already there)
+    for (int j = tid; j < n; j += T)
+      if ((L.dirty[j >> 5] >> (j & 31)) & 1u) cur.xi[j] = L.xs[j];
   }
   ncoll = team_sum<W>(L, ncoll, lane, wv);
   if (tid == 0) add_stats(dp->stats, live_sum, (unsigned long long)ncoll, nsub, steps_done);

@@ -11,8 +11,11 @@ arrived requests and a set of resident simulations:
   * every tick, ONE shared launch per step advances all resident simulations
     (sdm_batch_step), each by its own counter-based random numbers, so a
     simulation's result does not depend on what it is batched with;
-  * requests that arrive while a tick runs on the device are admitted at the
-    next tick boundary (admission work overlaps the device work);
+  * requests that arrive while a tick runs on the device are admitted while
+    it runs (their upload and validation go on a second stream, and the
+    library's set-up calls synchronise only that stream), and the next tick's
+    shared-launch tables are built and uploaded then too, so the host work of
+    a membership change overlaps the device work;
   * finished simulations are read back (moments), their slot and bytes freed,
     and their latency (completion - arrival) recorded.
 
@@ -84,7 +87,8 @@ class Server:
     executor: object with footprint(req, state), admit(req, state) -> handle,
       batch(handles) -> batch, step(batch, k) (enqueue), sync(),
       collect(handles) -> [result dict] (after sync), release(handle),
-      step_of(handle).
+      step_of(handle); optionally prepare(handles) -> batch (built while a
+      tick runs) and adopt(batch) (makes a prepared batch the current one).
     budget_bytes: device bytes the resident simulations may use.
     max_resident: resident slots.
     steps_per_tick: steps per shared launch sequence between admissions.
@@ -168,6 +172,8 @@ class Server:
                 o.status, o.admit_s = "running", self.clock() - t0
             st.max_resident = max(st.max_resident, len(resident))
 
+        prepared = None  # (members, batch) built while the previous tick ran
+        can_prepare = hasattr(self.ex, "prepare") and hasattr(self.ex, "adopt")
         while pending or waiting or resident:
             cancellations()
             if not resident:
@@ -182,8 +188,12 @@ class Server:
                     continue
             members = tuple(sorted(resident))
             if members != batch_members:
-                batch = self.ex.batch([resident[r][1] for r in members])
+                if prepared is not None and prepared[0] == members:
+                    batch = self.ex.adopt(prepared[1])
+                else:
+                    batch = self.ex.batch([resident[r][1] for r in members])
                 batch_members = members
+            prepared = None
             t_dev = self.clock()
             self.ex.step(batch, self.k)  # enqueue: one shared launch per step
             st.launches += self.k
@@ -191,6 +201,11 @@ class Server:
             finished = [r for r in members
                         if self.ex.step_of(resident[r][1]) >= resident[r][0].n_steps]
             admit_arrived()  # host admission work overlaps the device tick
+            if can_prepare:  # and so does building the next tick's batch
+                done = set(finished)
+                nxt = tuple(sorted(r for r in resident if r not in done))
+                if nxt and nxt != members:
+                    prepared = (nxt, self.ex.prepare([resident[r][1] for r in nxt]))
             self.ex.sync()
             st.device_busy_s += self.clock() - t_dev
             results = self.ex.collect([resident[r][1] for r in finished]) if finished else []
@@ -224,8 +239,10 @@ class GpuExecutor:
         self.device = device
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.admit_stream = torch.cuda.Stream()
-        self._batch = None
-        self._batch_ws = None
+        self._batch = None  # the batch the ticks run
+        self._next = None  # a batch prepared for the next tick
+        self._ws = [None, None]  # their workspaces (the current one is _ws[_cur])
+        self._cur = 0
 
     def footprint(self, req, state):
         B = self.B
@@ -249,16 +266,42 @@ class GpuExecutor:
         sim.n_live0 = int((state.xi > 0).sum())
         return sim
 
-    def batch(self, sims):
-        if self._batch is not None:
-            self.B.sdm_batch_free(self._batch)
-            self._batch = None
+    def _make(self, sims, slot, stream):
         handles = [s.handle for s in sims]
         nbytes = self.B.sdm_batch_workspace_bytes(handles)
-        if self._batch_ws is None or self._batch_ws.numel() < nbytes:
-            self._batch_ws = self.B.workspace_tensor(int(nbytes * 1.25) + 4096, self.device)
-        self._batch = self.B.sdm_batch_create(handles, self._batch_ws, self.stream)
+        if self._ws[slot] is None or self._ws[slot].numel() < nbytes:
+            self._ws[slot] = self.B.workspace_tensor(int(nbytes * 1.25) + 4096, self.device)
+        return self.B.sdm_batch_create(handles, self._ws[slot], stream)
+
+    def _free(self, b):
+        if b is not None:
+            self.B.sdm_batch_free(b)
+
+    def batch(self, sims):
+        """A batch for the next tick, built on the tick stream (after sync)."""
+        self._free(self._batch)
+        self._free(self._next)
+        self._batch = self._next = None
+        self._batch = self._make(sims, self._cur, self.stream)
         return self._batch
+
+    def prepare(self, sims):
+        """A batch for the next tick, built while the current tick runs: its
+        tables go to the other workspace (not in use by the running batch),
+        uploaded on the admission stream."""
+        self._free(self._next)
+        self._next = None
+        self._next = self._make(sims, 1 - self._cur, self.admit_stream)
+        return self._next
+
+    def adopt(self, b):
+        """Make a prepared batch current (the tick that used the old one has
+        been synchronised)."""
+        assert b is self._next
+        self._free(self._batch)
+        self._batch, self._next = b, None
+        self._cur = 1 - self._cur
+        return b
 
     def step(self, batch, k):
         self.B.sdm_batch_step(batch, k, self.stream)
@@ -294,9 +337,9 @@ class GpuExecutor:
         sim.close()
 
     def close(self):
-        if self._batch is not None:
-            self.B.sdm_batch_free(self._batch)
-            self._batch = None
+        self._free(self._batch)
+        self._free(self._next)
+        self._batch = self._next = None
 
 
 def serve_one_at_a_time(requests, state_of, executor, clock=time.perf_counter, sleep=time.sleep):

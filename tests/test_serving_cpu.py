@@ -190,3 +190,48 @@ def test_latency_accounting_virtual_clock(orc):
     stats = srv.run([req], I.request_state)
     o = stats.outcomes[req.rid]
     assert o.status == "done" and o.latency_s == pytest.approx(0.0, abs=0.011)
+
+
+class PreparingExecutor(OracleExecutor):
+    """Also builds the next tick's batch while a tick "runs" (prepare/adopt)."""
+
+    def __init__(self, orc, clock):
+        super().__init__(orc, clock)
+        self.prepared = 0
+        self.adopted = 0
+        self.current = None
+        self.pending = None
+
+    def batch(self, handles):
+        self.current, self.pending = list(handles), None
+        self.batches += 1
+        return self.current
+
+    def prepare(self, handles):
+        self.prepared += 1
+        self.pending = list(handles)
+        return self.pending
+
+    def adopt(self, b):
+        assert b is self.pending  # only the batch prepared last is adopted
+        self.adopted += 1
+        self.current, self.pending = b, None
+        return b
+
+
+def test_prepared_batches_are_adopted_and_results_unchanged(orc):
+    """When the next tick's membership is known while a tick runs (finishers
+    out, admissions in), the server has the executor build that batch then,
+    and uses it if nothing changed meanwhile; results equal the solo runs."""
+    clock = Clock()
+    ex = PreparingExecutor(orc, clock)
+    reqs = small_requests(20, seed=5)
+    srv = Server(ex, budget_bytes=10 ** 9, steps_per_tick=4, clock=clock, sleep=clock.sleep)
+    stats = srv.run(reqs, I.request_state)
+    assert stats.summary()["done"] == len(reqs)
+    assert ex.prepared > 0 and ex.adopted > 0
+    assert ex.adopted <= ex.prepared
+    for r in reqs:
+        ref = alone(orc, r)
+        o = stats.outcomes[r.rid]
+        assert np.array_equal(o.result["xi"], ref.xi) and np.array_equal(o.result["v"], ref.v)
