@@ -302,6 +302,23 @@ sdm_status sdm_displace(const sdm_displace_args* args, void* workspace, size_t w
                         void* stream);
 
 /*
+ * sdm_displace without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, checks, kernels and
+ * results as sdm_displace; the workspace is instead a file-scope device array
+ * of the library (9.5 MiB, held on each GPU the library runs on until the
+ * process ends), big enough for nx * nz <= sdm_displace_noalloc_max_cells()
+ * (2^17) cells: larger domains return SDM_ENOMEM and enqueue nothing.  The
+ * call allocates nothing (the array's device address is looked up once per
+ * device at the first call there).  Every call on one GPU uses the same
+ * array, whose contents are rewritten before they are read, so calls that
+ * overlap on one GPU (other streams, other host threads) race: serialise
+ * them.  Enqueue only.
+ */
+sdm_status sdm_displace_noalloc(const sdm_displace_args* args, void* stream);
+int64_t sdm_displace_noalloc_max_cells(void);
+
+/*
  * Test hook for the generator: out[4 i + w] = word w of Philox4x32-10 with
  * counter (c0 + i, c1, c2, c3) and key (seed mod 2^32, seed / 2^32), for
  * i < n (device buffer of 4 n uint32).  Enqueue only.

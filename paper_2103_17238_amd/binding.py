@@ -29,7 +29,8 @@ EXPORTED = [
     "sdm_debug_gamma_sink", "sdm_get_tuning", "sdm_set_tuning", "sdm_autotune_scratch_bytes",
     "sdm_autotune", "sdm_batch_workspace_bytes", "sdm_batch_create", "sdm_batch_step",
     "sdm_batch_free", "sdm_free", "sdm_strerror", "sdm_philox_fill", "sdm_kernel_values",
-    "sdm_rebind", "sdm_displace_workspace_bytes", "sdm_displace",
+    "sdm_rebind", "sdm_displace_workspace_bytes", "sdm_displace", "sdm_displace_noalloc",
+    "sdm_displace_noalloc_max_cells",
 ]
 
 
@@ -126,6 +127,8 @@ class sdm_displace_args(C.Structure):
 _sig("sdm_rebind", _S, _H, _P, _P, _P, _P, _P)
 _sig("sdm_displace_workspace_bytes", C.c_size_t, C.c_int32, C.c_int32)
 _sig("sdm_displace", _S, C.POINTER(sdm_displace_args), _P, C.c_size_t, _P)
+_sig("sdm_displace_noalloc", _S, C.POINTER(sdm_displace_args), _P)
+_sig("sdm_displace_noalloc_max_cells", C.c_int64)
 
 
 class SdmError(RuntimeError):
@@ -299,6 +302,19 @@ def sdm_displace(nx, nz, courant_x, courant_z, xi, v, attrs, pos, cell_off, xi_o
     _check("sdm_displace", _lib.sdm_displace(C.byref(a), _ptr(workspace),
                                              workspace.numel() * workspace.element_size(),
                                              _stream(stream)))
+
+
+def sdm_displace_noalloc(nx, nz, courant_x, courant_z, xi, v, attrs, pos, cell_off, xi_out,
+                         v_out, attrs_out, pos_out, cell_off_out, status, stream=None):
+    a = sdm_displace_args(int(nx), int(nz), int(attrs.shape[0]) if attrs is not None else 0, 0,
+                          int(xi.numel()), _ptr(courant_x), _ptr(courant_z), _ptr(xi), _ptr(v),
+                          _ptr(attrs), _ptr(pos), _ptr(cell_off), _ptr(xi_out), _ptr(v_out),
+                          _ptr(attrs_out), _ptr(pos_out), _ptr(cell_off_out), _ptr(status))
+    _check("sdm_displace_noalloc", _lib.sdm_displace_noalloc(C.byref(a), _stream(stream)))
+
+
+def sdm_displace_noalloc_max_cells() -> int:
+    return int(_lib.sdm_displace_noalloc_max_cells())
 
 
 def sdm_strerror(st: int) -> str:

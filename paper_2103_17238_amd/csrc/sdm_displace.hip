@@ -35,6 +35,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/sdm.h"
 
 namespace sdm {
@@ -328,9 +330,9 @@ using sdm::kDispWaves;
 using sdm::kOffBlock;
 using sdm::kScanThreads;
 constexpr size_t kAlignD = 256;
-inline size_t up(size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; }
+constexpr size_t up(size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; }
 
-size_t ws_bytes(int64_t C) {
+constexpr size_t ws_bytes(int64_t C) {
   const int64_t nblk = (C + kOffBlock - 1) / kOffBlock;
   return up(sizeof(uint32_t)) + 2 * up(sizeof(uint32_t) * 9 * (size_t)C) +
          up(sizeof(uint32_t) * (size_t)C) + 2 * up(sizeof(uint32_t) * (size_t)nblk) +
@@ -343,17 +345,8 @@ bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
   return na == 0 || nb == 0 || x + na <= y || y + nb <= x;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t sdm_displace_workspace_bytes(int32_t nx, int32_t nz) {
-  if (nx < 1 || nz < 1 || (int64_t)nx * nz > (int64_t)0x7FFFFFFF / 9) return 0;
-  return ws_bytes((int64_t)nx * nz);
-}
-
-sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t workspace_bytes,
-                        void* stream) {
+// Argument checks shared by both entry points; returns SDM_OK or the error.
+sdm_status check_args(const sdm_displace_args* g) {
   if (!g || g->nx < 1 || g->nz < 1 || (int64_t)g->nx * g->nz > (int64_t)0x7FFFFFFF / 9 ||
       g->n_attr < 0 || g->n_attr > 16 || g->reserved != 0 || g->n_slots < 0 ||
       g->n_slots >= 0xFFFFFFFFLL)
@@ -372,9 +365,13 @@ sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t work
   for (int i = 0; i < 5; ++i)
     for (int k = 0; k < 5; ++k)
       if (ins[i] && outs[k] && !disjoint(ins[i], nin[i], outs[k], nin[k])) return SDM_EINVAL;
-  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlignD) return SDM_EINVAL;
-  if (workspace_bytes < ws_bytes(C)) return SDM_ENOMEM;
+  return SDM_OK;
+}
 
+// The four kernels of one call over the workspace at w (ws_bytes(C) bytes,
+// every word written before it is read, so it needs no clearing).
+sdm_status launch_displace(const sdm_displace_args* g, char* w, hipStream_t st) {
+  const int64_t C = (int64_t)g->nx * g->nz, n = g->n_slots;
   sdm::DispState S{};
   S.nx = g->nx;
   S.nz = g->nz;
@@ -394,7 +391,6 @@ sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t work
   S.off_out = g->cell_off_out;
   S.status = g->status;
   const int64_t nblk = (C + kOffBlock - 1) / kOffBlock;
-  char* w = static_cast<char*>(workspace);
   S.err = reinterpret_cast<uint32_t*>(w);
   w += up(sizeof(uint32_t));
   S.cnt = reinterpret_cast<uint32_t*>(w);
@@ -409,7 +405,6 @@ sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t work
   w += up(sizeof(uint32_t) * (size_t)nblk);
   S.blk_off = reinterpret_cast<int64_t*>(w);
 
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const unsigned cells_grid = (unsigned)((C + kDispWaves - 1) / kDispWaves);
   hipLaunchKernelGGL(sdm::k_disp_count, dim3(cells_grid), dim3(64 * kDispWaves), 0, st, S);
   hipLaunchKernelGGL(sdm::k_disp_offsets, dim3((unsigned)nblk), dim3(kOffBlock), 0, st, S);
@@ -417,5 +412,69 @@ sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t work
   hipLaunchKernelGGL(sdm::k_disp_scatter, dim3(cells_grid), dim3(64 * kDispWaves), 0, st, S);
   return hipGetLastError() == hipSuccess ? SDM_OK : SDM_EDEVICE;
 }
+
+// Scratch of the allocation-free entry point: the workspace of a domain of up
+// to kScratchCells cells, in a file-scope device array.  Each GPU the library
+// runs on holds its own copy until the process ends; every call on one GPU
+// reuses it, so calls that overlap on one GPU race.  Host code never passes
+// the array's name to a kernel (in host code it only stands for the symbol):
+// its device address, per device, comes from hipGetSymbolAddress.
+constexpr int64_t kScratchCells = int64_t(1) << 17;
+constexpr size_t kScratchBytes = ws_bytes(kScratchCells);  // 9.5 MiB
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of `scratch` (looked up once per device)
+char* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sdm_displace_workspace_bytes(int32_t nx, int32_t nz) {
+  if (nx < 1 || nz < 1 || (int64_t)nx * nz > (int64_t)0x7FFFFFFF / 9) return 0;
+  return ws_bytes((int64_t)nx * nz);
+}
+
+sdm_status sdm_displace(const sdm_displace_args* g, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  const sdm_status r = check_args(g);
+  if (r != SDM_OK) return r;
+  const int64_t C = (int64_t)g->nx * g->nz;
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlignD) return SDM_EINVAL;
+  if (workspace_bytes < ws_bytes(C)) return SDM_ENOMEM;
+  return launch_displace(g, static_cast<char*>(workspace), reinterpret_cast<hipStream_t>(stream));
+}
+
+sdm_status sdm_displace_noalloc(const sdm_displace_args* g, void* stream) {
+  const sdm_status r = check_args(g);
+  if (r != SDM_OK) return r;
+  const int64_t C = (int64_t)g->nx * g->nz;
+  if (C > kScratchCells) return SDM_ENOMEM;  // ws_bytes grows with C: it fits
+  char* w = scratch_address();
+  if (!w) return SDM_EDEVICE;
+  return launch_displace(g, w, reinterpret_cast<hipStream_t>(stream));
+}
+
+int64_t sdm_displace_noalloc_max_cells(void) { return kScratchCells; }
 
 }  // extern "C"
