@@ -309,16 +309,37 @@ __device__ __forceinline__ void scan_store(uint32_t* cnt, int first, int per, in
 // ---------------------------------------------------------------------------
 constexpr int pow2_ceil(int x) { return x <= 1 ? 1 : 2 * pow2_ceil((x + 1) / 2); }
 
+// One colliding pair of a (sub)step, listed for the volume and attribute
+// phase: X_k = fma(g, X_j, X_k) for every extensive X, and X_j = X_k too when
+// the pair split equally.
+struct alignas(16) Coll {
+  uint16_t j, k;   // cell-local slots: j the larger multiplicity, k the other
+  uint32_t split;  // 1: equal-multiplicity split
+  double gd;       // g
+};
+
 template <int CAP>
 struct alignas(16) CellLds {
   long long xs[CAP];  // multiplicities (slot order)
   double rs[CAP];     // kernel sizes (slot order)
-  uint32_t tmp[CAP];  // bucketed (key << nbits | slot), then uint16 permutation
-  uint32_t cnt[pow2_ceil(CAP) + 4];  // bucket counters / starts
+  // tmp: bucketed (key << nbits | slot), then the uint16 permutation; cnt:
+  // bucket counters / starts.  Once a pair pass has the permutation in
+  // registers, tmp and cnt together hold the list of colliding pairs.
+  uint32_t tmp[CAP];
+  uint32_t cnt[pow2_ceil(CAP) + 4];
   uint32_t dirty[CAP / 32];  // LDS-resident steps: multiplicities to write back
+  int nlist;                 // colliding pairs listed in this (sub)step
   int red_i[8];              // cross-wave reductions
   double red_d[8];
 };
+
+template <int CAP>
+__device__ __forceinline__ Coll* coll_list(CellLds<CAP>& L) {
+  static_assert(sizeof(L.tmp) % 16 == 0, "the list starts 16-byte aligned");
+  static_assert((sizeof(L.tmp) + sizeof(L.cnt)) / sizeof(Coll) >= CAP / 2,
+                "every pair of a full cell can be listed");
+  return reinterpret_cast<Coll*>(L.tmp);
+}
 
 template <int W>
 __device__ __forceinline__ void team_sync() {
@@ -477,6 +498,7 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       if ((live[i] >> e) & 1) perm[rk[i][e]] = (uint16_t)(4 * (T * i + tid) + e);
+  if (tid == 0) L.nlist = 0;
   team_sync<W>();
 }
 
@@ -553,6 +575,10 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
     if (MODE == kPassPmax) return pmax;
   }
   const bool in_lds = MODE != kPassPlain;
+  // every thread's permutation reads are done before the list overwrites it
+  team_sync<W>();
+  Coll* list = coll_list(L);
+  long long* xi_g = reinterpret_cast<long long*>(dp->xi + o0);
 #pragma unroll
   for (int i = 0; i < I4; ++i) {
     const int h = T * i + tid;
@@ -574,21 +600,61 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
         sink[sink_base + 2 * m + 1] = gamma;
       }
       if (gamma > 0) {
+        // multiplicities now (LDS-resident or in place); volumes and
+        // attributes in the listed phase below
         *ncoll += 1;
         const long long xa = L.xs[a], xb = L.xs[bb];
-        const double va = vg[a], vb = vg[bb];
-        if (!in_lds) {
-          update_pair(dp->xi + o0, vg, a, bb, xa, xb, va, vb, gamma, dp->attrs, dp->n_slots,
-                      dp->n_attr, o0 + a, o0 + bb);
-        } else {
-          double na = va, nbv = vb;
-          *ndead += update_pair(L.xs, vg, a, bb, xa, xb, va, vb, gamma, dp->attrs, dp->n_slots,
-                                dp->n_attr, o0 + a, o0 + bb, &na, &nbv);
-          L.rs[a] = size_of(kind, na);
-          L.rs[bb] = size_of(kind, nbv);
-          atomicOr(&L.dirty[a >> 5], 1u << (a & 31));
-          atomicOr(&L.dirty[bb >> 5], 1u << (bb & 31));
+        const bool a_is_j = xa >= xb;  // ties: the pair's first member
+        const int j = a_is_j ? a : bb, k = a_is_j ? bb : a;
+        const long long xj = a_is_j ? xa : xb, xk = a_is_j ? xb : xa;
+        long long g = gamma;
+        if (g > 1) {
+          const long long ratio = xj / xk;
+          g = g < ratio ? g : ratio;
         }
+        const long long rest = xj - g * xk;
+        long long* xt = in_lds ? L.xs : xi_g;
+        uint32_t split = 0;
+        if (rest > 0) {
+          xt[j] = rest;
+        } else {  // equal-multiplicity split; xk = 1 leaves slot j empty
+          const long long hh = xk >> 1;
+          xt[j] = hh;
+          xt[k] = xk - hh;
+          split = 1;
+          if (in_lds) *ndead += hh == 0 ? 1 : 0;
+        }
+        if (in_lds) {
+          atomicOr(&L.dirty[j >> 5], 1u << (j & 31));
+          atomicOr(&L.dirty[k >> 5], 1u << (k & 31));
+        }
+        const int at = atomicAdd(&L.nlist, 1);
+        Coll cl;
+        cl.j = (uint16_t)j;
+        cl.k = (uint16_t)k;
+        cl.split = split;
+        cl.gd = (double)g;
+        list[at] = cl;
+      }
+    }
+  }
+  team_sync<W>();
+  {  // volumes and attributes of every listed pair, spread over the team:
+     // one round of independent global loads for up to T (pair, field) tasks
+    const int nl = L.nlist;
+    const int F = 1 + dp->n_attr;
+    const int ntask = nl * F;
+    for (int t = tid; t < ntask; t += T) {
+      const int li = t / F, f = t - li * F;
+      const Coll cl = list[li];
+      double* X = f == 0 ? vg : dp->attrs + (int64_t)(f - 1) * dp->n_slots + o0;
+      const double val = fma(cl.gd, X[cl.j], X[cl.k]);
+      X[cl.k] = val;
+      if (cl.split) X[cl.j] = val;
+      if (in_lds && f == 0) {  // the size of an SD follows its volume
+        const double sz = size_of(kind, val);
+        L.rs[cl.k] = sz;
+        if (cl.split) L.rs[cl.j] = sz;
       }
     }
   }
