@@ -93,10 +93,25 @@ __device__ __forceinline__ double size_of(int kind, double v) {
   return kind == 0 ? v : cbrt(kVolToR3 * v);
 }
 
+// fall_speed for the cell kernels: the square-root regime is taken only when
+// some lane of the wavefront has a radius above 600 um (a wave-uniform
+// branch), so that the compiler cannot turn it into a select that computes
+// the square root for every SD.  Same bits as fall_speed.
+__device__ __forceinline__ double fall_speed_w(double r) {
+  double u = fmin(kU1 * r * r, kU2 * r);
+  if (__builtin_amdgcn_ballot_w64(r > 6.0e-4) != 0) {
+    // an empty volatile statement makes this block non-speculatable: without
+    // it the compiler computes the square root for every lane and selects
+    __asm__ volatile("");
+    if (r > 6.0e-4) u = fmin(u, kU3 * sqrt(r));
+  }
+  return u;
+}
+
 __device__ __forceinline__ double pair_kernel(int kind, double b, double sa, double sb) {
   if (kind == 0) return b * (sa + sb);
   const double rs = sa + sb;
-  return kPi * (rs * rs) * fabs(fall_speed(sa) - fall_speed(sb));
+  return kPi * (rs * rs) * fabs(fall_speed_w(sa) - fall_speed_w(sb));
 }
 
 __device__ __forceinline__ long long collisions(double p, double phi, uint32_t* status) {
@@ -309,18 +324,23 @@ __device__ __forceinline__ void scan_store(uint32_t* cnt, int first, int per, in
 // ---------------------------------------------------------------------------
 constexpr int pow2_ceil(int x) { return x <= 1 ? 1 : 2 * pow2_ceil((x + 1) / 2); }
 
-// One colliding pair of a (sub)step, listed for the volume and attribute
-// phase: X_k = fma(g, X_j, X_k) for every extensive X, and X_j = X_k too when
-// the pair split equally.
+// One colliding pair of a (sub)step.  The pair pass lists (a, b, gamma);
+// the multiplicity phase rewrites the entry as (j, k, split, g): j the
+// member with the larger multiplicity, k the other, split = 1 for an equal
+// split; the volume and attribute phase then sets X_k = fma(g, X_j, X_k) for
+// every extensive X, and X_j = X_k too when the pair split equally.
 struct alignas(16) Coll {
-  uint16_t j, k;   // cell-local slots: j the larger multiplicity, k the other
-  uint32_t split;  // 1: equal-multiplicity split
-  double gd;       // g
+  uint16_t j, k;
+  uint32_t split;
+  long long g;
 };
 
 template <int CAP>
 struct alignas(16) CellLds {
-  long long xs[CAP];  // multiplicities (slot order)
+  // multiplicities as doubles: every multiplicity is an integer below 2^53
+  // (sdm_init checks it, and the update only lowers them), so the doubles
+  // are exact and compare and convert exactly
+  double xd[CAP];
   double rs[CAP];     // kernel sizes (slot order)
   // tmp: bucketed (key << nbits | slot), then the uint16 permutation; cnt:
   // bucket counters / starts.  Once a pair pass has the permutation in
@@ -421,12 +441,12 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
     if (4 * g < n) {
       const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)c, s, 2u * u), k0, k1);
       const uint32_t kr[4] = {w.x, w.y, w.z, w.w};
-      const longlong2 x01 = *reinterpret_cast<const longlong2*>(&L.xs[4 * g]);
-      const longlong2 x23 = *reinterpret_cast<const longlong2*>(&L.xs[4 * g + 2]);
-      const long long xv[4] = {x01.x, x01.y, x23.x, x23.y};
+      const double2 x01 = *reinterpret_cast<const double2*>(&L.xd[4 * g]);
+      const double2 x23 = *reinterpret_cast<const double2*>(&L.xd[4 * g + 2]);
+      const double xv[4] = {x01.x, x01.y, x23.x, x23.y};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const bool lv = 4 * g + e < n && xv[e] > 0;
+        const bool lv = 4 * g + e < n && xv[e] > 0.0;
         live[i] |= lv ? 1u << e : 0u;
         bk[i][e] = kr[e] >> sh;
         me[i][e] = (kr[e] << nbits) | (uint32_t)(4 * g + e);
@@ -541,7 +561,7 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
   if (MODE != kPassAdapt) {
     // every pair's slots and sizes first (slots past the pairs clamped into
     // the cell and masked), then the arithmetic
-    long long xv[I4][4];
+    double xv[I4][4];
     double sv[I4][4];
 #pragma unroll
     for (int i = 0; i < I4; ++i) {
@@ -554,7 +574,7 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const uint32_t j = min(sl[e], (uint32_t)CAP - 1u);
-        xv[i][e] = L.xs[j];
+        xv[i][e] = L.xd[j];
         sv[i][e] = L.rs[j];
       }
     }
@@ -565,9 +585,8 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
       if (2 * h >= P) continue;
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        const long long xa = xv[i][2 * e], xb = xv[i][2 * e + 1];
         const double kv = pair_kernel(kind, bgol, sv[i][2 * e], sv[i][2 * e + 1]);
-        const double pp = ((double)(xa > xb ? xa : xb) * kv) * S;
+        const double pp = (fmax(xv[i][2 * e], xv[i][2 * e + 1]) * kv) * S;
         R.pre[i][e] = (2 * h + e < P) ? pp : 0.0;
         if (MODE == kPassPmax && 2 * h + e < P) pmax = fmax(pmax, pp * q);
       }
@@ -599,56 +618,66 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
         sink[sink_base + 2 * m] = (int64_t)((uint64_t)a | ((uint64_t)bb << 32));
         sink[sink_base + 2 * m + 1] = gamma;
       }
-      if (gamma > 0) {
-        // multiplicities now (LDS-resident or in place); volumes and
-        // attributes in the listed phase below
+      if (gamma > 0) {  // listed; the updates follow in two dense phases
         *ncoll += 1;
-        const long long xa = L.xs[a], xb = L.xs[bb];
-        const bool a_is_j = xa >= xb;  // ties: the pair's first member
-        const int j = a_is_j ? a : bb, k = a_is_j ? bb : a;
-        const long long xj = a_is_j ? xa : xb, xk = a_is_j ? xb : xa;
-        long long g = gamma;
-        if (g > 1) {
-          const long long ratio = xj / xk;
-          g = g < ratio ? g : ratio;
-        }
-        const long long rest = xj - g * xk;
-        long long* xt = in_lds ? L.xs : xi_g;
-        uint32_t split = 0;
-        if (rest > 0) {
-          xt[j] = rest;
-        } else {  // equal-multiplicity split; xk = 1 leaves slot j empty
-          const long long hh = xk >> 1;
-          xt[j] = hh;
-          xt[k] = xk - hh;
-          split = 1;
-          if (in_lds) *ndead += hh == 0 ? 1 : 0;
-        }
-        if (in_lds) {
-          atomicOr(&L.dirty[j >> 5], 1u << (j & 31));
-          atomicOr(&L.dirty[k >> 5], 1u << (k & 31));
-        }
         const int at = atomicAdd(&L.nlist, 1);
         Coll cl;
-        cl.j = (uint16_t)j;
-        cl.k = (uint16_t)k;
-        cl.split = split;
-        cl.gd = (double)g;
+        cl.j = (uint16_t)a;
+        cl.k = (uint16_t)bb;
+        cl.split = 0;
+        cl.g = gamma;
         list[at] = cl;
       }
     }
   }
   team_sync<W>();
+  const int nl = L.nlist;
+  // multiplicities: one thread per listed pair
+  for (int li = tid; li < nl; li += T) {
+    Coll cl = list[li];
+    const int a = cl.j, bb = cl.k;
+    const double xa = L.xd[a], xb = L.xd[bb];
+    const bool a_is_j = xa >= xb;  // ties: the pair's first member
+    const int j = a_is_j ? a : bb, k = a_is_j ? bb : a;
+    const long long xj = (long long)(a_is_j ? xa : xb), xk = (long long)(a_is_j ? xb : xa);
+    long long g = cl.g;
+    if (g > 1) {
+      const long long ratio = xj / xk;
+      g = g < ratio ? g : ratio;
+    }
+    const long long rest = xj - g * xk;
+    long long nj = rest, nk = xk;
+    cl.split = 0;
+    if (rest <= 0) {  // equal-multiplicity split; xk = 1 leaves slot j empty
+      nj = xk >> 1;
+      nk = xk - nj;
+      cl.split = 1;
+      if (in_lds) *ndead += nj == 0 ? 1 : 0;
+    }
+    if (in_lds) {
+      L.xd[j] = (double)nj;
+      L.xd[k] = (double)nk;
+      atomicOr(&L.dirty[j >> 5], 1u << (j & 31));
+      atomicOr(&L.dirty[k >> 5], 1u << (k & 31));
+    } else {
+      xi_g[j] = nj;
+      if (cl.split) xi_g[k] = nk;
+    }
+    cl.j = (uint16_t)j;
+    cl.k = (uint16_t)k;
+    cl.g = g;
+    list[li] = cl;
+  }
+  team_sync<W>();
   {  // volumes and attributes of every listed pair, spread over the team:
      // one round of independent global loads for up to T (pair, field) tasks
-    const int nl = L.nlist;
     const int F = 1 + dp->n_attr;
     const int ntask = nl * F;
     for (int t = tid; t < ntask; t += T) {
       const int li = t / F, f = t - li * F;
       const Coll cl = list[li];
       double* X = f == 0 ? vg : dp->attrs + (int64_t)(f - 1) * dp->n_slots + o0;
-      const double val = fma(cl.gd, X[cl.j], X[cl.k]);
+      const double val = fma((double)cl.g, X[cl.j], X[cl.k]);
       X[cl.k] = val;
       if (cl.split) X[cl.j] = val;
       if (in_lds && f == 0) {  // the size of an SD follows its volume
@@ -727,7 +756,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
   for (int it = 0; it < IT; ++it) {
     const int j = it * T + tid;
     if (it * T < n && j < n) {
-      L.xs[j] = xr[it];
+      L.xd[j] = (double)xr[it];
       L.rs[j] = xr[it] > 0 ? size_of(kind, vr[it]) : 0.0;
       mylive += xr[it] > 0 ? 1 : 0;
     }
@@ -816,7 +845,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
     team_sync<W>();
     // write back the multiplicities that changed (volumes are already there)
     for (int j = tid; j < n; j += T)
-      if ((L.dirty[j >> 5] >> (j & 31)) & 1u) cur.xi[j] = L.xs[j];
+      if ((L.dirty[j >> 5] >> (j & 31)) & 1u) cur.xi[j] = (long long)L.xd[j];
   }
   ncoll = team_sum<W>(L, ncoll, lane, wv);
   if (tid == 0) add_stats(dp->stats, live_sum, (unsigned long long)ncoll, nsub, steps_done);
