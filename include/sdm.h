@@ -114,14 +114,17 @@ typedef struct {
                                 up to 256 slots and the mid-size cells run on a second stream
                                 beside the larger classes and the big-cell kernels */
   int32_t waves_per_cell;    /* 1, 2, 4 or 8: wavefronts in the workgroup of one cell */
-  int32_t big_bucket_target; /* cells on the big-cell path: expected SDs per sort bucket,
-                                32..1024 */
+  int32_t big_bucket_target; /* cells on the big-cell path: expected SDs per bucket (a key
+                                range ordered by one workgroup), 32..1024 */
   int32_t lpt_order;         /* 1: dispatch cells by descending size (adaptive cells: at the
                                 first step; after it they go by the substeps they took in
                                 the step before, most first) */
   int32_t mid_max_slots;     /* cells of 513..mid_max_slots slots (<= 16384) get one workgroup
-                                each (mid-size kernel); larger ones take the multi-pass
-                                big-cell path; 0 sends every cell above 512 there */
+                                each (mid-size kernel); larger ones take the big-cell path
+                                (two launches per step); 0 sends every cell above 512 there */
+  int32_t big_bucket_cap;    /* big-cell path: entries stored per bucket before the rest go to
+                                an overflow list (still exact, slower); 0 = twice
+                                big_bucket_target, else 1..2 x big_bucket_target */
 } sdm_tuning;
 
 /*

@@ -57,6 +57,7 @@ class sdm_tuning(C.Structure):
         ("big_bucket_target", C.c_int32),
         ("lpt_order", C.c_int32),
         ("mid_max_slots", C.c_int32),
+        ("big_bucket_cap", C.c_int32),
     ]
 
     def as_dict(self):

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -25,7 +26,6 @@
 
 using sdm::BigBucket;
 using sdm::BigChunk;
-using sdm::BigPairBlock;
 using sdm::BigTask;
 using sdm::PlanDev;
 using sdm::SimDesc;
@@ -47,6 +47,7 @@ sdm_tuning default_tuning() {
   t.big_bucket_target = 256;
   t.lpt_order = 1;
   t.mid_max_slots = sdm::kMidCapMax;
+  t.big_bucket_cap = 0;
   return t;
 }
 
@@ -54,8 +55,16 @@ bool tuning_ok(const sdm_tuning& t) {
   const int w = t.waves_per_cell;
   return (w == 1 || w == 2 || w == 4 || w == 8) && t.big_bucket_target >= sdm::kMinBucketTarget &&
          t.big_bucket_target <= 1024 && (t.wave_class_mask & ~sdm::kClassAll) == 0 &&
-         t.mid_max_slots >= 0 && t.mid_max_slots <= sdm::kMidCapMax;
+         t.mid_max_slots >= 0 && t.mid_max_slots <= sdm::kMidCapMax && t.big_bucket_cap >= 0 &&
+         t.big_bucket_cap <= 2 * t.big_bucket_target;
 }
+
+// entries of a big cell's bucket region (the tuning's cap, else twice the
+// expected bucket size)
+int big_cap(const sdm_tuning& t) {
+  return t.big_bucket_cap > 0 ? t.big_bucket_cap : 2 * t.big_bucket_target;
+}
+constexpr int64_t kBigRegionSlack = 2 * 1024;  // region entries beyond 2 n per big cell, at most
 
 }  // namespace
 
@@ -106,6 +115,45 @@ struct sdm_sim {
 static sdm_status rebind_host(sdm_sim* s, int64_t* xi, double* v, double* attrs,
                               const int64_t* cell_off, hipStream_t st);
 
+// Pinned host memory for the device-to-host reads of the set-up calls (cell
+// offsets, the validation flag): a copy into pageable memory goes through
+// the runtime's staging buffer, which can make it wait for work on other
+// streams.  One buffer per process, grown as needed, guarded by a mutex;
+// growing it (a pinned allocation) is the only step that may synchronise.
+struct PinnedReadback {
+  std::mutex mu;
+  void* buf = nullptr;
+  size_t bytes = 0;
+  ~PinnedReadback() {
+    if (buf) (void)hipHostFree(buf);
+  }
+};
+static PinnedReadback g_pinned;
+
+// Copies `bytes` from device `src` to host `dst` through the pinned buffer,
+// ordered on `st`, and synchronises `st`.
+static bool read_back(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  std::lock_guard<std::mutex> lock(g_pinned.mu);
+  if (g_pinned.bytes < bytes) {
+    if (g_pinned.buf) (void)hipHostFree(g_pinned.buf);
+    g_pinned.buf = nullptr;
+    g_pinned.bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&g_pinned.buf, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    g_pinned.bytes = want;
+  }
+  if (hipMemcpyAsync(g_pinned.buf, src, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  std::memcpy(dst, g_pinned.buf, bytes);
+  return true;
+}
+
 // Refreshes the host copy of the offsets after device-side rebinds.  The
 // device offsets are final once sdm_rebind returned (it synchronised the
 // stream that wrote them), so a blocking copy suffices; no device-wide
@@ -133,8 +181,8 @@ struct Tables {
   std::vector<BigTask> big;
   std::vector<BigChunk> chunks;
   std::vector<BigBucket> buckets;
-  std::vector<BigPairBlock> pblocks;
-  int64_t tmp_total = 0;
+  int64_t tmp_total = 0;     // slots of big cells (overflow and order entries)
+  int64_t region_total = 0;  // bucket-region entries
   int64_t bucket_total = 0;
   int64_t n_wave_total() const {
     int64_t n = 0;
@@ -171,22 +219,23 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
       }
       if (ms[i]->cfg.adaptive) T.adaptive_big = true;
       BigTask t{};
+      t.xi = ms[i]->xi + off[c];
+      t.v = ms[i]->v + off[c];
       t.sim = i;
       t.cell = c;
       t.n_slots = (int32_t)n;
-      const int64_t want = (n + tu.big_bucket_target - 1) / tu.big_bucket_target;
-      t.bbits = want <= 1 ? 0 : ceil_log2(want);
+      t.nb = (int32_t)std::max<int64_t>(1, (n + tu.big_bucket_target - 1) / tu.big_bucket_target);
+      t.cap = big_cap(tu);
+      t.region_base = T.region_total;
+      T.region_total += (int64_t)t.nb * t.cap;
       t.tmp_base = T.tmp_total;
       T.tmp_total += n;
       t.bucket_base = (int32_t)T.bucket_total;
-      const int nb = 1 << t.bbits;
-      T.bucket_total += nb + 1;
+      T.bucket_total += t.nb;
       const int ti = (int)T.big.size();
       T.big.push_back(t);
       for (int64_t f = 0; f < n; f += sdm::kChunk) T.chunks.push_back({ti, (int32_t)f});
-      for (int b = 0; b < nb; ++b) T.buckets.push_back({ti, b});
-      const int64_t groups = (n + 3) / 4;
-      for (int64_t g = 0; g < groups; g += 256) T.pblocks.push_back({ti, (int32_t)g});
+      for (int b = 0; b < t.nb; ++b) T.buckets.push_back({ti, b});
     }
   }
   // plain-mode cells first (one kernel each), largest first within a mode
@@ -215,9 +264,8 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
 
 struct Layout {
   size_t desc, wave[sdm::kNumClasses], wave_alt[sdm::kNumClasses], order_flag[sdm::kNumClasses],
-      order_cnt[sdm::kNumClasses],
-      mid[sdm::kNumMid], big, chunks, buckets, pblocks, bucket_cnt, bucket_start, task_live,
-      task_nlive, tmp, ord, total;
+      order_cnt[sdm::kNumClasses], mid[sdm::kNumMid], big, chunks, buckets, cnt[2], ovf_cnt[2],
+      region, ovf, ord, total;
 };
 
 static Layout layout_of(int n_members, const Tables& T) {
@@ -241,12 +289,12 @@ static Layout layout_of(int n_members, const Tables& T) {
   L.big = take(sizeof(BigTask) * std::max<size_t>(T.big.size(), 1));
   L.chunks = take(sizeof(BigChunk) * std::max<size_t>(T.chunks.size(), 1));
   L.buckets = take(sizeof(BigBucket) * std::max<size_t>(T.buckets.size(), 1));
-  L.pblocks = take(sizeof(BigPairBlock) * std::max<size_t>(T.pblocks.size(), 1));
-  L.bucket_cnt = take(sizeof(uint32_t) * std::max<int64_t>(T.bucket_total, 1));
-  L.bucket_start = take(sizeof(uint32_t) * std::max<int64_t>(T.bucket_total, 1));
-  L.task_live = take(sizeof(uint32_t) * std::max<size_t>(T.big.size(), 1));
-  L.task_nlive = take(sizeof(uint32_t) * std::max<size_t>(T.big.size(), 1));
-  L.tmp = take(sizeof(unsigned long long) * std::max<int64_t>(T.tmp_total, 1));
+  for (int k = 0; k < 2; ++k) {
+    L.cnt[k] = take(sizeof(uint32_t) * std::max<int64_t>(T.bucket_total, 1));
+    L.ovf_cnt[k] = take(sizeof(uint32_t) * std::max<size_t>(T.big.size(), 1));
+  }
+  L.region = take(sizeof(unsigned long long) * std::max<int64_t>(T.region_total, 1));
+  L.ovf = take(sizeof(unsigned long long) * std::max<int64_t>(T.tmp_total, 1));
   L.ord = take(sizeof(uint32_t) * std::max<int64_t>(T.tmp_total, 1));
   L.total = o;
   return L;
@@ -267,8 +315,12 @@ static size_t plan_bytes_worst(const std::vector<sdm_sim*>& ms) {
       const int64_t n = s->off[c + 1] - s->off[c];
       n_mid += (n > sdm::kWaveCapMax && n <= sdm::kMidCapMax) ? 1 : 0;
     }
+  // bucket regions: nb x cap <= (n / target + 1) 2 target <= 2 n + 2 target
+  // entries for any target; the smallest target gives the most counters
+  const size_t region_extra =
+      sizeof(unsigned long long) * (size_t)kBigRegionSlack * T.big.size();
   return layout_of((int)ms.size(), T).total + align_up(sizeof(sdm::CellTask) * n_mid) +
-         (4 * sdm::kNumClasses + sdm::kNumMid) * kAlign;
+         align_up(region_extra) + (4 * sdm::kNumClasses + sdm::kNumMid) * kAlign;
 }
 
 struct Plan {
@@ -280,7 +332,8 @@ struct Plan {
   PlanDev dev{};
   std::vector<SimDesc> desc;  // host copy of the device descriptors
   uint32_t counter = 0;       // launch step of the next step
-  uint32_t flip = 0;          // steps launched since the tables were built
+  uint32_t flip = 0;          // launches since the tables were built
+  uint32_t big_steps = 0;     // big-cell steps launched since the tables were built
   sdm::SideStream side;       // created at the first step
   std::shared_ptr<Busy> busy;  // event recorded after each step call, created at the first
   Plan() = default;
@@ -386,14 +439,14 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   d.n_chunks = (int)p->T.chunks.size();
   d.buckets = reinterpret_cast<const BigBucket*>(w + L.buckets);
   d.n_buckets = (int)p->T.buckets.size();
-  d.pblocks = reinterpret_cast<const BigPairBlock*>(w + L.pblocks);
-  d.n_pblocks = (int)p->T.pblocks.size();
-  d.bucket_cnt = reinterpret_cast<uint32_t*>(w + L.bucket_cnt);
-  d.bucket_start = reinterpret_cast<uint32_t*>(w + L.bucket_start);
-  d.task_live = reinterpret_cast<uint32_t*>(w + L.task_live);
-  d.task_nlive = reinterpret_cast<uint32_t*>(w + L.task_nlive);
-  d.tmp = reinterpret_cast<unsigned long long*>(w + L.tmp);
+  for (int k = 0; k < 2; ++k) {
+    d.cnt[k] = reinterpret_cast<uint32_t*>(w + L.cnt[k]);
+    d.ovf_cnt[k] = reinterpret_cast<uint32_t*>(w + L.ovf_cnt[k]);
+  }
+  d.region = reinterpret_cast<unsigned long long*>(w + L.region);
+  d.ovf = reinterpret_cast<unsigned long long*>(w + L.ovf);
   d.ord = reinterpret_cast<uint32_t*>(w + L.ord);
+  p->big_steps = 0;
 
   // the old tables may still be read by steps enqueued on `st`
   HIP_TRY(hipStreamSynchronize(st));
@@ -413,11 +466,10 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   HIP_TRY(upload(const_cast<BigTask*>(d.big), p->T.big, st));
   HIP_TRY(upload(const_cast<BigChunk*>(d.chunks), p->T.chunks, st));
   HIP_TRY(upload(const_cast<BigBucket*>(d.buckets), p->T.buckets, st));
-  HIP_TRY(upload(const_cast<BigPairBlock*>(d.pblocks), p->T.pblocks, st));
-  if (p->T.bucket_total > 0)
-    HIP_TRY(hipMemsetAsync(d.bucket_cnt, 0, sizeof(uint32_t) * p->T.bucket_total, st));
-  if (!p->T.big.empty())
-    HIP_TRY(hipMemsetAsync(d.task_live, 0, sizeof(uint32_t) * p->T.big.size(), st));
+  for (int k = 0; k < 2 && !p->T.big.empty(); ++k) {  // both sets of counters start at zero
+    HIP_TRY(hipMemsetAsync(d.cnt[k], 0, sizeof(uint32_t) * p->T.bucket_total, st));
+    HIP_TRY(hipMemsetAsync(d.ovf_cnt[k], 0, sizeof(uint32_t) * p->T.big.size(), st));
+  }
   if (sync_end) HIP_TRY(hipStreamSynchronize(st));
   return SDM_OK;
 }
@@ -475,9 +527,10 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
   }
   for (int64_t k = 0; k < active;) {  // up to kFuseMax steps per launch
     const int f = (int)std::min<int64_t>(sdm::kFuseMax, active - k);
-    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->flip++, f,
+    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->flip++, p->big_steps, f,
                          p->tuning.waves_per_cell, st, p->side) != hipSuccess)
       return SDM_EDEVICE;
+    p->big_steps += (uint32_t)f;
     k += f;
   }
   p->counter += (uint32_t)n_steps;
@@ -559,13 +612,13 @@ static size_t plan_bytes_bound(const sdm_config* c) {
   }
   take(sizeof(BigTask) * (size_t)std::max<int64_t>(nbig, 1));
   take(sizeof(BigChunk) * (size_t)(ns / sdm::kChunk + nbig + 1));
-  const int64_t nbk = ns / (sdm::kMinBucketTarget / 2) + 2 * nbig + 1;
+  const int64_t nbk = ns / sdm::kMinBucketTarget + nbig + 1;
   take(sizeof(BigBucket) * (size_t)nbk);
-  take(sizeof(BigPairBlock) * (size_t)(ns / 1024 + nbig + 1));
-  take(sizeof(uint32_t) * (size_t)(nbk + nbig));
-  take(sizeof(uint32_t) * (size_t)(nbk + nbig));
-  take(sizeof(uint32_t) * (size_t)std::max<int64_t>(nbig, 1));
-  take(sizeof(uint32_t) * (size_t)std::max<int64_t>(nbig, 1));
+  for (int k = 0; k < 2; ++k) {
+    take(sizeof(uint32_t) * (size_t)nbk);
+    take(sizeof(uint32_t) * (size_t)std::max<int64_t>(nbig, 1));
+  }
+  take(sizeof(unsigned long long) * (size_t)(2 * ns + kBigRegionSlack * nbig + 1));
   take(sizeof(unsigned long long) * (size_t)std::max<int64_t>(ns, 1));
   take(sizeof(uint32_t) * (size_t)std::max<int64_t>(ns, 1));
   (void)T;
@@ -605,10 +658,7 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
   s->attrs = cfg->n_attr > 0 ? attrs : nullptr;
   s->cell_off = cell_off;
   s->off.resize((size_t)cfg->n_cells + 1);
-  if (hipMemcpyAsync(s->off.data(), cell_off, sizeof(int64_t) * s->off.size(),
-                     hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess) {
-    (void)hipGetLastError();
+  if (!read_back(s->off.data(), cell_off, sizeof(int64_t) * s->off.size(), st)) {
     delete s;
     return SDM_EDEVICE;
   }
@@ -663,11 +713,11 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
                            hipMemcpyHostToDevice, st) == hipSuccess;
   const sdm_status r = ok ? plan_setup(s->plan, st, false) : SDM_EDEVICE;
   ok = ok && r == SDM_OK &&
-       sdm::launch_validate(xi, v, cfg->n_slots, s->d_status, st) == hipSuccess &&
-       hipMemcpyAsync(&flags, s->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, st) ==
-           hipSuccess;
-  // pb, flags and the plan's host tables are alive until here
-  const bool synced = hipStreamSynchronize(st) == hipSuccess;
+       sdm::launch_validate(xi, v, cfg->n_slots, s->d_status, st) == hipSuccess;
+  // the flag read-back synchronises st: pb and the plan's host tables are
+  // alive until here
+  const bool synced = ok ? read_back(&flags, s->d_status, sizeof(uint32_t), st)
+                        : hipStreamSynchronize(st) == hipSuccess && false;
   if (!ok || !synced) {
     (void)hipGetLastError();
     delete s->plan;
@@ -1009,9 +1059,9 @@ static bool cache_lookup(const char* path, const std::string& key, sdm_tuning* t
     if (std::sscanf(line,
                     "{\"key\": \"%511[^\"]\", \"wave_class_mask\": %d, \"waves_per_cell\": %d, "
                     "\"big_bucket_target\": %d, \"lpt_order\": %d, \"mid_max_slots\": %d, "
-                    "\"ms_per_step\": %lf}",
+                    "\"big_bucket_cap\": %d, \"ms_per_step\": %lf}",
                     k, &x.wave_class_mask, &x.waves_per_cell, &x.big_bucket_target,
-                    &x.lpt_order, &x.mid_max_slots, &ms) == 7 &&
+                    &x.lpt_order, &x.mid_max_slots, &x.big_bucket_cap, &ms) == 8 &&
         key == k && tuning_ok(x)) {
       *t = x;  // the last matching line wins
       found = true;
@@ -1027,9 +1077,9 @@ static void cache_store(const char* path, const std::string& key, const sdm_tuni
   std::fprintf(f,
                "{\"key\": \"%s\", \"wave_class_mask\": %d, \"waves_per_cell\": %d, "
                "\"big_bucket_target\": %d, \"lpt_order\": %d, \"mid_max_slots\": %d, "
-               "\"ms_per_step\": %.6f}\n",
+               "\"big_bucket_cap\": %d, \"ms_per_step\": %.6f}\n",
                key.c_str(), t.wave_class_mask, t.waves_per_cell, t.big_bucket_target,
-               t.lpt_order, t.mid_max_slots, ms);
+               t.lpt_order, t.mid_max_slots, t.big_bucket_cap, ms);
   std::fclose(f);
 }
 
@@ -1109,7 +1159,7 @@ extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_byt
     const std::vector<int> waves = any_small ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1};
     for (int m : masks)
       for (int wpb : waves)
-        for (int tg : targets) cands.push_back({m, wpb, tg, 1, mm});
+        for (int tg : targets) cands.push_back({m, wpb, tg, 1, mm, 0});
   }
 
   hipEvent_t e0, e1;

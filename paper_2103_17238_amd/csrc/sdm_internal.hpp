@@ -13,8 +13,7 @@ constexpr int kNumClasses = 5;    // workgroup-per-cell capacities 64, 128, 256,
 constexpr int kWaveCapMax = 512;  // cells above this go to the mid-size or big-cell path
 constexpr int kNumMid = 4;        // mid-size capacities 2048, 4096, 8192, 16384 slots
 constexpr int kMidCapMax = 16384;
-constexpr int kChunk = 1024;      // slots per block in the big-cell key passes
-constexpr int kBucketCap = 1024;  // big-cell bucket entries staged in LDS by one wave
+constexpr int kChunk = 4096;      // slots per block of the big-cell key pass
 constexpr int kMinBucketTarget = 32;
 constexpr int kOrderBlock = 1024;  // tasks per block of the dispatch-order partition
 constexpr int kOrderGroups = 4;    // dispatch-order groups by substeps taken
@@ -65,15 +64,20 @@ struct CellTask {
   int32_t pad;
 };
 
-// A cell of more than kWaveCapMax slots, sorted through global buckets.
+// A cell above the mid-size limit: its live slots are spread over nb
+// buckets (key ranges) of cap entries each, then each bucket is ordered and
+// paired by one workgroup.
 struct BigTask {
+  int64_t* xi;  // first slot of the cell
+  double* v;
+  int64_t region_base;  // first entry of the cell's nb x cap bucket regions
+  int64_t tmp_base;     // first entry of the cell in the overflow and order buffers
   int32_t sim;
   int32_t cell;
-  int64_t tmp_base;     // first entry of this cell in the keyed-entry and order buffers
-  int32_t bucket_base;  // first of this cell's (1 << bbits) + 1 bucket counters
-  int32_t bbits;        // log2 of the bucket count
+  int32_t bucket_base;  // first of the cell's nb bucket counters
+  int32_t nb;
+  int32_t cap;
   int32_t n_slots;
-  int32_t pad;
 };
 
 struct BigChunk {  // kChunk consecutive slots of one big cell
@@ -84,11 +88,6 @@ struct BigChunk {  // kChunk consecutive slots of one big cell
 struct BigBucket {  // one bucket of one big cell
   int32_t task;
   int32_t bucket;
-};
-
-struct BigPairBlock {  // 256 pair groups (4 sorted positions each) of one big cell
-  int32_t task;
-  int32_t first_group;
 };
 
 // Device view of a launch plan (all pointers carved from a workspace).
@@ -114,14 +113,13 @@ struct PlanDev {
   int n_chunks;
   const BigBucket* buckets;
   int n_buckets;
-  const BigPairBlock* pblocks;
-  int n_pblocks;
-  uint32_t* bucket_cnt;
-  uint32_t* bucket_start;
-  uint32_t* task_live;
-  uint32_t* task_nlive;
-  unsigned long long* tmp;
-  uint32_t* ord;
+  // two sets of bucket and overflow counters: a step fills one and clears
+  // the other for the next step
+  uint32_t* cnt[2];
+  uint32_t* ovf_cnt[2];
+  unsigned long long* region;  // bucket regions
+  unsigned long long* ovf;     // overflow entries (a full bucket's extra entries)
+  uint32_t* ord;               // order of a bucket ranked in global memory
 };
 
 // second stream (and fork/join events) for concurrent class launches
@@ -135,9 +133,10 @@ struct SideStream {
 // workgroup-per-cell classes in one launch each (several steps fused), the
 // mid-size and big cells one step per launch.  flip: launches made on this
 // plan since its tables were built (selects which of the two adaptive task
-// lists is read).
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
-                       int waves_per_cell, hipStream_t st, const SideStream& side);
+// lists is read); big_step: big-cell steps launched since then (selects the
+// set of bucket counters).
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, uint32_t big_step,
+                       int nsteps, int waves_per_cell, hipStream_t st, const SideStream& side);
 hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
                           double* attr_sums, const double* edges, int n_bins, double* spectrum,
                           hipStream_t st);

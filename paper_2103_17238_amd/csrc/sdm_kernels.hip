@@ -75,13 +75,7 @@ __device__ __forceinline__ double fall_speed(double r) {
   return fmin(u12, kU3 * sqrt(r));
 }
 
-__device__ __forceinline__ double coal_kernel(int kind, double b, double va, double vb) {
-  if (kind == 0) return b * (va + vb);  // Golovin additive kernel
-  const double ra = cbrt(kVolToR3 * va);
-  const double rb = cbrt(kVolToR3 * vb);
-  const double rs = ra + rb;
-  return kPi * (rs * rs) * fabs(fall_speed(ra) - fall_speed(rb));  // geometric sweep-out, E = 1
-}
+
 
 // The per-SD quantity the kernel is built from ("size"): the radius for the
 // geometric kernel, the volume itself for Golovin's.  A cell kernel keeps it
@@ -112,6 +106,11 @@ __device__ __forceinline__ double pair_kernel(int kind, double b, double sa, dou
   if (kind == 0) return b * (sa + sb);
   const double rs = sa + sb;
   return kPi * (rs * rs) * fabs(fall_speed_w(sa) - fall_speed_w(sb));
+}
+
+// the kernel from two volumes (Golovin additive; geometric sweep-out, E = 1)
+__device__ __forceinline__ double coal_kernel(int kind, double b, double va, double vb) {
+  return pair_kernel(kind, b, size_of(kind, va), size_of(kind, vb));
 }
 
 __device__ __forceinline__ long long collisions(double p, double phi, uint32_t* status) {
@@ -1104,238 +1103,406 @@ __global__ void __launch_bounds__(64 * W) k_cells_mid(const SimDesc* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Big cells (above the mid-size limit): global bucket sort by the top key bits.
+// Big cells (above the mid-size limit): two launches per step.
+//
+// k_big_keys: every live slot's key goes to bucket floor(key nb / 2^32) of
+// its cell (nb buckets, a monotone map of the key, so buckets are key
+// ranges in order); the entry (key << 32 | slot) is stored at the bucket's
+// next free place in a fixed-capacity region, or, when the bucket is full,
+// appended to the cell's overflow list.
+// k_big_bucket: one workgroup per bucket.  The bucket's first position in
+// the cell's permutation is the sum of the counts of the buckets before it;
+// its entries are ordered in LDS (a sub-bucket scatter on the key's position
+// inside the bucket range, then an exact rank inside each sub-bucket), and
+// the workgroup takes every pair whose first member sits at an even
+// position of its range: the partner is the next entry, or, for the last
+// entry, the smallest entry of the next non-empty bucket.  A bucket longer
+// than its region or than the LDS stage is ranked in global memory instead
+// (exact, slow, flagged).  The counters of one step are cleared by the
+// other step's bucket kernel (two sets, alternating).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t bucket_of(uint32_t key, int bbits) {
-  return bbits ? (key >> (32 - bbits)) : 0u;
+constexpr int kBigKeyThreads = 256;
+constexpr int kBigKeyGroups = kChunk / (4 * kBigKeyThreads);  // Philox groups per thread
+constexpr int kBigKeyLdsBuckets = 8192;  // bucket histogram of one block in LDS
+static_assert(kBigKeyGroups * 4 * kBigKeyThreads == kChunk, "a block covers one chunk");
+constexpr int kBigThreads = 256;
+constexpr int kBigSortCap = 1024;  // entries one workgroup orders in LDS
+
+__device__ __forceinline__ uint32_t key_bucket(uint32_t key, uint32_t nb) {
+  return (uint32_t)(((unsigned long long)key * nb) >> 32);
 }
 
-// B1: bucket counts and live count; 256 threads x 4 slots per block
-__global__ void __launch_bounds__(256) k_big_count(const SimDesc* __restrict__ descs,
-                                                   const BigTask* __restrict__ big,
-                                                   const BigChunk* __restrict__ chunks,
-                                                   uint32_t* __restrict__ bucket_cnt,
-                                                   uint32_t* __restrict__ task_live,
-                                                   uint32_t k_abs) {
-  __shared__ int red[4];
+// Each block takes kChunk slots (kBigKeyGroups Philox groups of 4 per
+// thread).  Its bucket counts are made in LDS, then one global atomic per
+// (block, bucket) reserves the block's places in the bucket: a bucket
+// counter sees as many atomics as the cell has blocks, not as many as it
+// has entries (counters of one cell are hit from every XCD).  Cells with
+// more buckets than the LDS histogram holds take one global atomic per
+// entry.
+__global__ void __launch_bounds__(kBigKeyThreads) k_big_keys(
+    const SimDesc* __restrict__ descs, const BigTask* __restrict__ big,
+    const BigChunk* __restrict__ chunks, uint32_t* __restrict__ cnt,
+    uint32_t* __restrict__ ovf_cnt, unsigned long long* __restrict__ region,
+    unsigned long long* __restrict__ ovf, uint32_t k_abs) {
+  __shared__ uint32_t hist[kBigKeyLdsBuckets];
   const BigChunk ch = chunks[blockIdx.x];
   const BigTask tk = big[ch.task];
   const SimDesc* dp = descs + tk.sim;
   const uint32_t s = k_abs + dp->step_delta;
   if (s >= dp->step_limit) return;
-  const int64_t o0 = dp->cell_off[tk.cell];
-  const int g = ch.first / 4 + threadIdx.x;
-  const int j0 = 4 * g;
-  int live = 0;
-  if (j0 < tk.n_slots) {
+  const uint32_t nb = (uint32_t)tk.nb;
+  const bool local = nb <= (uint32_t)kBigKeyLdsBuckets;
+  if (local) {
+    for (uint32_t i = threadIdx.x; i < nb; i += kBigKeyThreads) hist[i] = 0;
+    __syncthreads();
+  }
+  uint32_t kk[kBigKeyGroups][4], bkt[kBigKeyGroups][4], pos[kBigKeyGroups][4];
+#pragma unroll
+  for (int r = 0; r < kBigKeyGroups; ++r) {
+    const int g = ch.first / 4 + r * kBigKeyThreads + (int)threadIdx.x;
+    const int j0 = 4 * g;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pos[r][e] = 0xFFFFFFFFu;
+    if (j0 >= tk.n_slots || j0 >= ch.first + kChunk) continue;
+    long long xv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xv[e] = j0 + e < tk.n_slots ? tk.xi[j0 + e] : 0;
     const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)tk.cell, s, 0u), dp->seed_lo,
                            dp->seed_hi);
-    const uint32_t kk[4] = {w.x, w.y, w.z, w.w};
+    kk[r][0] = w.x;
+    kk[r][1] = w.y;
+    kk[r][2] = w.z;
+    kk[r][3] = w.w;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int j = j0 + e;
-      if (j < tk.n_slots && dp->xi[o0 + j] > 0) {
-        atomicAdd(&bucket_cnt[tk.bucket_base + bucket_of(kk[e], tk.bbits)], 1u);
-        ++live;
+      bkt[r][e] = key_bucket(kk[r][e], nb);
+      if (xv[e] > 0)
+        pos[r][e] = local ? atomicAdd(&hist[bkt[r][e]], 1u)
+                          : atomicAdd(&cnt[tk.bucket_base + bkt[r][e]], 1u);
+    }
+  }
+  if (local) {  // this block's places: one global atomic per bucket it uses
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += kBigKeyThreads) {
+      const uint32_t h = hist[i];
+      if (h) hist[i] = atomicAdd(&cnt[tk.bucket_base + i], h);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kBigKeyGroups; ++r) {
+    const int j0 = 4 * (ch.first / 4 + r * kBigKeyThreads + (int)threadIdx.x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (pos[r][e] == 0xFFFFFFFFu) continue;
+      const uint32_t at = local ? hist[bkt[r][e]] + pos[r][e] : pos[r][e];
+      const unsigned long long ent = ((unsigned long long)kk[r][e] << 32) | (unsigned)(j0 + e);
+      if (at < (uint32_t)tk.cap) {
+        region[tk.region_base + (int64_t)bkt[r][e] * tk.cap + at] = ent;
+      } else {
+        const uint32_t q = atomicAdd(&ovf_cnt[ch.task], 1u);
+        ovf[tk.tmp_base + q] = ent;
       }
     }
   }
-  live = wave_sum(live);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = live;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int tot = red[0] + red[1] + red[2] + red[3];
-    if (tot) atomicAdd(&task_live[ch.task], (uint32_t)tot);
-  }
 }
 
-// B2: exclusive scan of each big cell's bucket counts
-__global__ void __launch_bounds__(256) k_big_scan(const SimDesc* __restrict__ descs,
-                                                  const BigTask* __restrict__ big,
-                                                  const uint32_t* __restrict__ bucket_cnt,
-                                                  uint32_t* __restrict__ bucket_start,
-                                                  uint32_t* __restrict__ task_live,
-                                                  uint32_t* __restrict__ task_nlive,
-                                                  uint32_t k_abs) {
-  __shared__ int part[256];
-  const BigTask tk = big[blockIdx.x];
-  const SimDesc* dp = descs + tk.sim;
-  const uint32_t s = k_abs + dp->step_delta;
-  if (s >= dp->step_limit) return;
-  const int nb = 1 << tk.bbits;
-  const int per = (nb + 255) / 256;
-  const int first = threadIdx.x * per;
-  int local = 0;
-  for (int i = 0; i < per; ++i)
-    if (first + i < nb) local += (int)bucket_cnt[tk.bucket_base + first + i];
-  part[threadIdx.x] = local;
-  __syncthreads();
-  for (int d = 1; d < 256; d <<= 1) {  // inclusive scan in LDS
-    const int t = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
-    __syncthreads();
-    part[threadIdx.x] += t;
-    __syncthreads();
-  }
-  int run = part[threadIdx.x] - local;
-  for (int i = 0; i < per; ++i) {
-    if (first + i < nb) {
-      const int cv = (int)bucket_cnt[tk.bucket_base + first + i];
-      bucket_start[tk.bucket_base + first + i] = (uint32_t)run;
-      run += cv;
-    }
-  }
-  if (threadIdx.x == 0) {
-    const uint32_t live = task_live[blockIdx.x];
-    bucket_start[tk.bucket_base + nb] = live;
-    task_nlive[blockIdx.x] = live;
-    task_live[blockIdx.x] = 0;
-  }
-}
+struct alignas(16) BigLds {
+  unsigned long long ent[kBigSortCap];  // the bucket's entries (unordered)
+  uint32_t sc[kBigSortCap + 4];         // sub-bucket counters / starts
+  uint32_t ord[kBigSortCap];            // slots in permutation order
+  // colliding pairs of one round of kBigThreads pairs: slots j, k (the
+  // larger multiplicity first), g, equal split
+  uint32_t lj[kBigThreads], lk[kBigThreads], lsplit[kBigThreads];
+  long long lg[kBigThreads];
+  int nlist;
+  int red[kBigThreads / 64][4];
+  unsigned long long red64[kBigThreads / 64];
+  uint32_t next_slot;  // partner of the last entry (next bucket's smallest)
+};
 
-// B3: scatter (key << 32 | slot) into the buckets; leaves the counts at zero
-__global__ void __launch_bounds__(256) k_big_scatter(const SimDesc* __restrict__ descs,
-                                                     const BigTask* __restrict__ big,
-                                                     const BigChunk* __restrict__ chunks,
-                                                     uint32_t* __restrict__ bucket_cnt,
-                                                     const uint32_t* __restrict__ bucket_start,
-                                                     unsigned long long* __restrict__ tmp,
-                                                     uint32_t k_abs) {
-  const BigChunk ch = chunks[blockIdx.x];
-  const BigTask tk = big[ch.task];
-  const SimDesc* dp = descs + tk.sim;
-  const uint32_t s = k_abs + dp->step_delta;
-  if (s >= dp->step_limit) return;
-  const int64_t o0 = dp->cell_off[tk.cell];
-  const int g = ch.first / 4 + threadIdx.x;
-  const int j0 = 4 * g;
-  if (j0 >= tk.n_slots) return;
-  const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)tk.cell, s, 0u), dp->seed_lo,
-                         dp->seed_hi);
-  const uint32_t kk[4] = {w.x, w.y, w.z, w.w};
+// exclusive scan of L.sc[0, n) in place (n <= kBigSortCap), L.sc[n] = total;
+// kBigThreads threads, 4 counters each, fixed order
+__device__ __forceinline__ void big_scan(BigLds& L, int n) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int first = 4 * tid;
+  uint32_t c4[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) c4[e] = first + e < n ? L.sc[first + e] : 0u;
+  const int local = (int)(c4[0] + c4[1] + c4[2] + c4[3]);
+  int run = wave_excl_scan(local, lane);
+  if (lane == 63) L.red[wv][3] = run + local;
+  __syncthreads();
+  for (int k = 0; k < wv; ++k) run += L.red[k][3];
+  if (tid == kBigThreads - 1) L.sc[n] = (uint32_t)(run + local);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int j = j0 + e;
-    if (j < tk.n_slots && dp->xi[o0 + j] > 0) {
-      const uint32_t b = bucket_of(kk[e], tk.bbits);
-      const uint32_t pos = atomicSub(&bucket_cnt[tk.bucket_base + b], 1u) - 1u;
-      tmp[tk.tmp_base + bucket_start[tk.bucket_base + b] + pos] =
-          ((unsigned long long)kk[e] << 32) | (unsigned)j;
-    }
+    if (first + e < n) L.sc[first + e] = (uint32_t)run;
+    run += (int)c4[e];
   }
+  __syncthreads();
 }
 
-// B4: exact rank inside each bucket, one wave per bucket
-__global__ void __launch_bounds__(512) k_big_rank(const SimDesc* __restrict__ descs,
-                                                  const BigTask* __restrict__ big,
-                                                  const BigBucket* __restrict__ buckets,
-                                                  int n_buckets,
-                                                  const uint32_t* __restrict__ bucket_start,
-                                                  const unsigned long long* __restrict__ tmp,
-                                                  uint32_t* __restrict__ ord, uint32_t k_abs) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int gbk = blockIdx.x * (blockDim.x >> 6) + wv;
-  if (gbk >= n_buckets) return;
-  unsigned long long* e = reinterpret_cast<unsigned long long*>(smem) + wv * kBucketCap;
-  const BigBucket bk = buckets[gbk];
-  const BigTask tk = big[bk.task];
-  const SimDesc* dp = descs + tk.sim;
-  const uint32_t s = k_abs + dp->step_delta;
-  if (s >= dp->step_limit) return;
-  const int st = (int)bucket_start[tk.bucket_base + bk.bucket];
-  const int en = (int)bucket_start[tk.bucket_base + bk.bucket + 1];
-  const int len = en - st;
-  const unsigned long long* src = tmp + tk.tmp_base + st;
-  uint32_t* dst = ord + tk.tmp_base + st;
-  if (len <= kBucketCap) {
-    for (int i = lane; i < len; i += 64) e[i] = src[i];
-    wave_sync();
-    for (int i0 = 0; i0 < len; i0 += 64) {
-      const int i = i0 + lane;
-      const unsigned long long me = i < len ? e[i] : 0ull;
-      int r = 0;
-      for (int qq = 0; qq < len; ++qq) r += (e[qq] < me) ? 1 : 0;
-      if (i < len) dst[r] = (uint32_t)(me & 0xFFFFFFFFull);
-    }
-  } else {  // rare: bucket larger than the LDS stage, rank from global memory
-    if (lane == 0) atomicOr(dp->status, kFlagBucketOverflow);
-    for (int i0 = 0; i0 < len; i0 += 64) {
-      const int i = i0 + lane;
-      const unsigned long long me = i < len ? src[i] : 0ull;
-      int r = 0;
-      for (int qq = 0; qq < len; ++qq) r += (src[qq] < me) ? 1 : 0;
-      if (i < len) dst[r] = (uint32_t)(me & 0xFFFFFFFFull);
-    }
+// block-wide sums of two values (fixed order)
+__device__ __forceinline__ void block_sum2(BigLds& L, int& a, int& b) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) {
+    L.red[wv][0] = a;
+    L.red[wv][1] = b;
   }
-}
-
-// B5: pairs over the global order; one thread per pair group (pairs 2h, 2h+1)
-__global__ void __launch_bounds__(256) k_big_pairs(const SimDesc* __restrict__ descs,
-                                                   const BigTask* __restrict__ big,
-                                                   const BigPairBlock* __restrict__ pblocks,
-                                                   const uint32_t* __restrict__ task_nlive,
-                                                   const uint32_t* __restrict__ ord,
-                                                   uint32_t k_abs) {
-  __shared__ int red[4];
-  const BigPairBlock pb = pblocks[blockIdx.x];
-  const BigTask tk = big[pb.task];
-  const SimDesc* dp = descs + tk.sim;
-  const uint32_t s = k_abs + dp->step_delta;
-  if (s >= dp->step_limit) return;
-  const int64_t o0 = dp->cell_off[tk.cell];
-  const int h = pb.first_group + threadIdx.x;
-  const int nlive = (int)task_nlive[pb.task];
-  const int P = nlive >> 1;
-  int ncoll = 0;
-  int64_t* sink = dp->sink;
-  const int64_t sink_base = sink ? 2 * dp->pair_base[tk.cell] : 0;
-  if (sink) {
-    for (int e = 0; e < 2; ++e) {
-      const int m = 2 * h + e;
-      if (m >= P && m < (tk.n_slots >> 1)) {
-        sink[sink_base + 2 * m] = -1;
-        sink[sink_base + 2 * m + 1] = -1;
-      }
-    }
-  }
-  if (2 * h < P) {
-    const double S = (double)((nlive & 1) ? nlive : nlive - 1);
-    const uint4 w = philox(make_uint4((uint32_t)h, (uint32_t)tk.cell, s, 1u), dp->seed_lo,
-                           dp->seed_hi);
-    const uint32_t* o = ord + tk.tmp_base;
-    int64_t* xi = dp->xi + o0;
-    double* v = dp->v + o0;
+  __syncthreads();
+  a = b = 0;
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int m = 2 * h + e;
-      if (m >= P) break;
-      const int a = (int)o[2 * m], bb = (int)o[2 * m + 1];
+  for (int k = 0; k < kBigThreads / 64; ++k) {
+    a += L.red[k][0];
+    b += L.red[k][1];
+  }
+  __syncthreads();
+}
+
+// The smallest entry of bucket nbk (its region part and its overflow entries).
+__device__ unsigned long long bucket_min(const BigTask& tk, const uint32_t* cnt,
+                                         const uint32_t* ovf_cnt, int task,
+                                         const unsigned long long* region,
+                                         const unsigned long long* ovf, int nbk, BigLds& L) {
+  const uint32_t len = cnt[tk.bucket_base + nbk];
+  const uint32_t in_reg = min(len, (uint32_t)tk.cap);
+  unsigned long long m = ~0ull;
+  for (uint32_t i = threadIdx.x; i < in_reg; i += kBigThreads)
+    m = min(m, region[tk.region_base + (int64_t)nbk * tk.cap + i]);
+  if (len > (uint32_t)tk.cap) {
+    const uint32_t no = ovf_cnt[task];
+    for (uint32_t i = threadIdx.x; i < no; i += kBigThreads) {
+      const unsigned long long e = ovf[tk.tmp_base + i];
+      if ((int)key_bucket((uint32_t)(e >> 32), (uint32_t)tk.nb) == nbk) m = min(m, e);
+    }
+  }
+  // block min
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long t = __shfl_xor(m, o);
+    m = min(m, t);
+  }
+  if (lane == 0) L.red64[wv] = m;
+  __syncthreads();
+  unsigned long long r = ~0ull;
+#pragma unroll
+  for (int k = 0; k < kBigThreads / 64; ++k) r = min(r, L.red64[k]);
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kBigThreads) k_big_bucket(
+    const SimDesc* __restrict__ descs, const BigTask* __restrict__ big,
+    const BigBucket* __restrict__ buckets, uint32_t* __restrict__ cnt,
+    uint32_t* __restrict__ ovf_cnt, uint32_t* __restrict__ cnt_next,
+    uint32_t* __restrict__ ovf_cnt_next, const unsigned long long* __restrict__ region,
+    const unsigned long long* __restrict__ ovf, uint32_t* __restrict__ gord, uint32_t k_abs) {
+  __shared__ BigLds L;
+  const int tid = threadIdx.x;
+  const BigBucket bk = buckets[blockIdx.x];
+  const BigTask tk = big[bk.task];
+  const int b = bk.bucket;
+  // the other set of counters is cleared for the next step, skipped or not
+  if (tid == 0) {
+    cnt_next[tk.bucket_base + b] = 0;
+    if (b == 0) ovf_cnt_next[bk.task] = 0;
+  }
+  const SimDesc* dp = descs + tk.sim;
+  const uint32_t s = k_abs + dp->step_delta;
+  if (s >= dp->step_limit) return;
+  const int nb = tk.nb;
+  // this bucket's start and the cell's live count
+  int before = 0, total = 0;
+  for (int i = tid; i < nb; i += kBigThreads) {
+    const int c_ = (int)cnt[tk.bucket_base + i];
+    before += i < b ? c_ : 0;
+    total += c_;
+  }
+  block_sum2(L, before, total);
+  const int nlive = total, start = before;
+  const int len = (int)cnt[tk.bucket_base + b];
+  const int P = nlive >> 1;
+  const int c = tk.cell;
+  int64_t* sink = dp->sink;
+  const int64_t sink_base = sink ? 2 * dp->pair_base[c] : 0;
+  if (sink && b == 0)  // unused pair entries of the cell
+    for (int m = P + tid; m < (tk.n_slots >> 1); m += kBigThreads) {
+      sink[sink_base + 2 * m] = -1;
+      sink[sink_base + 2 * m + 1] = -1;
+    }
+  if (tid == 0) L.nlist = 0;
+  // first entry whose pair this bucket takes, and whether any pair is taken
+  const int i0 = start & 1;
+  const bool any_pair = len > i0 && (start + i0) / 2 < P;
+  const bool fast = len <= tk.cap && len <= kBigSortCap;
+  uint32_t* gsorted = gord + tk.tmp_base + start;  // slow path: slots in order
+  if (any_pair) {
+    if (fast) {
+      // order the entries in LDS: sub-buckets on the key's place inside
+      // this bucket's key range, then an exact rank inside each sub-bucket
+      const int sbits = len <= 1 ? 0 : 32 - __clz(len - 1);
+      const int nsb = 1 << sbits;
+      // scale < 2^(31 + 10): the product with a 32-bit key needs 128 bits
+      const unsigned long long scale = (unsigned long long)(uint32_t)nb << sbits;
+      for (int i = tid; i < nsb + 1; i += kBigThreads) L.sc[i] = 0;
+      constexpr int PER = kBigSortCap / kBigThreads;
+      unsigned long long me[PER];
+      uint32_t sub[PER], pos[PER];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int i = r * kBigThreads + tid;
+        me[r] = 0;
+        if (i < len) {
+          me[r] = region[tk.region_base + (int64_t)b * tk.cap + i];
+          // monotone in the key: (key nb 2^sbits) >> 32 = b 2^sbits + sub
+          const unsigned long long key = me[r] >> 32;
+          const unsigned long long lo = key * scale, hi = __umul64hi(key, scale);
+          sub[r] = (uint32_t)((hi << 32) | (lo >> 32)) - ((uint32_t)b << sbits);
+          pos[r] = atomicAdd(&L.sc[sub[r]], 1u);
+        }
+      }
+      __syncthreads();
+      big_scan(L, nsb);
+      uint32_t st[PER], ln[PER];
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int i = r * kBigThreads + tid;
+        st[r] = ln[r] = 0;
+        if (i < len) {
+          st[r] = L.sc[sub[r]];
+          ln[r] = L.sc[sub[r] + 1] - st[r];
+          L.ent[st[r] + pos[r]] = me[r];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int i = r * kBigThreads + tid;
+        if (i < len) {
+          uint32_t rk = st[r];
+          for (uint32_t k = 0; k < ln[r]; ++k) rk += L.ent[st[r] + k] < me[r] ? 1u : 0u;
+          L.ord[rk] = (uint32_t)(me[r] & 0xFFFFFFFFull);
+        }
+      }
+    } else {  // slow path: rank every entry against the whole bucket in global memory
+      if (tid == 0) atomicOr(dp->status, kFlagBucketOverflow);
+      const int in_reg = min(len, tk.cap);
+      const uint32_t no = len > tk.cap ? ovf_cnt[bk.task] : 0u;
+      const unsigned long long* reg = region + tk.region_base + (int64_t)b * tk.cap;
+      const unsigned long long* ov = ovf + tk.tmp_base;
+      auto rank_of = [&](unsigned long long e) {
+        uint32_t rk = 0;
+        for (int k = 0; k < in_reg; ++k) rk += reg[k] < e ? 1u : 0u;
+        for (uint32_t k = 0; k < no; ++k) {
+          const unsigned long long f = ov[k];
+          if ((int)key_bucket((uint32_t)(f >> 32), (uint32_t)nb) == b && f < e) ++rk;
+        }
+        return rk;
+      };
+      for (int i = tid; i < in_reg; i += kBigThreads) {
+        const unsigned long long e = reg[i];
+        gsorted[rank_of(e)] = (uint32_t)(e & 0xFFFFFFFFull);
+      }
+      for (uint32_t i = tid; i < no; i += kBigThreads) {
+        const unsigned long long e = ov[i];
+        if ((int)key_bucket((uint32_t)(e >> 32), (uint32_t)nb) == b)
+          gsorted[rank_of(e)] = (uint32_t)(e & 0xFFFFFFFFull);
+      }
+      __threadfence_block();
+    }
+    // partner of the last entry: the smallest entry of the next non-empty bucket
+    if (((start + len) & 1) && (start + len - 1) / 2 < P) {
+      int nbk = b + 1;
+      while (nbk < nb && cnt[tk.bucket_base + nbk] == 0) ++nbk;
+      unsigned long long m = ~0ull;
+      if (nbk < nb) m = bucket_min(tk, cnt, ovf_cnt, bk.task, region, ovf, nbk, L);
+      if (tid == 0) L.next_slot = (uint32_t)(m & 0xFFFFFFFFull);
+    }
+  }
+  __syncthreads();
+  // pairs: positions start + i with i = i0, i0 + 2, ...; rounds of
+  // kBigThreads pairs, each followed by the dense update of its collisions
+  int ncoll = 0;
+  const double S = (double)((nlive & 1) ? nlive : nlive - 1);
+  int64_t* xi = tk.xi;
+  double* v = tk.v;
+  const int64_t o0 = tk.xi - dp->xi;
+  const int npairs = any_pair ? min((len - i0 + 1) >> 1, P - ((start + i0) >> 1)) : 0;
+  for (int base = 0; base < npairs; base += kBigThreads) {
+    const int t = base + tid;
+    if (t < npairs) {
+      const int i = i0 + 2 * t;
+      const int m = (start + i) >> 1;
+      const int a = (int)(fast ? L.ord[i] : gsorted[i]);
+      const int bb = (int)(i + 1 < len ? (fast ? L.ord[i + 1] : gsorted[i + 1]) : L.next_slot);
       const long long xa = xi[a], xb = xi[bb];
-      const double va = v[a], vb = v[bb];
-      const double kv = coal_kernel(dp->kernel, dp->b, va, vb);
+      const double kv = coal_kernel(dp->kernel, dp->b, v[a], v[bb]);
       const double p = (((double)(xa > xb ? xa : xb) * kv) * S) * dp->q;
-      const double phi = e == 0 ? uniform53(w.x, w.y) : uniform53(w.z, w.w);
+      const uint4 w = philox(make_uint4((uint32_t)(m >> 1), (uint32_t)c, s, 1u), dp->seed_lo,
+                             dp->seed_hi);
+      const double phi = (m & 1) == 0 ? uniform53(w.x, w.y) : uniform53(w.z, w.w);
       const long long gamma = collisions(p, phi, dp->status);
       if (sink) {
         sink[sink_base + 2 * m] = (int64_t)((uint64_t)a | ((uint64_t)bb << 32));
         sink[sink_base + 2 * m + 1] = gamma;
       }
-      if (gamma > 0) {
+      if (gamma > 0) {  // multiplicities now, volumes and attributes listed
         ++ncoll;
-        update_pair(xi, v, a, bb, xa, xb, va, vb, gamma, dp->attrs, dp->n_slots, dp->n_attr,
-                    o0 + a, o0 + bb);
+        const bool a_is_j = xa >= xb;  // ties: the pair's first member
+        const long long xj = a_is_j ? xa : xb, xk = a_is_j ? xb : xa;
+        long long g = gamma;
+        if (g > 1) {
+          const long long ratio = xj / xk;
+          g = g < ratio ? g : ratio;
+        }
+        const int j = a_is_j ? a : bb, k = a_is_j ? bb : a;
+        const long long rest = xj - g * xk;
+        uint32_t split = 0;
+        if (rest > 0) {
+          xi[j] = rest;
+        } else {  // equal-multiplicity split
+          const long long h = xk >> 1;
+          xi[j] = h;
+          xi[k] = xk - h;
+          split = 1;
+        }
+        const int at = atomicAdd(&L.nlist, 1);
+        L.lj[at] = (uint32_t)j;
+        L.lk[at] = (uint32_t)k;
+        L.lsplit[at] = split;
+        L.lg[at] = g;
       }
     }
+    __syncthreads();
+    const int nl = L.nlist;
+    const int F = 1 + dp->n_attr;
+    for (int u = tid; u < nl * F; u += kBigThreads) {  // one round of loads
+      const int li = u / F, f = u - li * F;
+      const int j = (int)L.lj[li], k = (int)L.lk[li];
+      double* X = f == 0 ? v : dp->attrs + (int64_t)(f - 1) * dp->n_slots + o0;
+      const double val = fma((double)L.lg[li], X[j], X[k]);
+      X[k] = val;
+      if (L.lsplit[li]) X[j] = val;
+    }
+    __syncthreads();
+    if (tid == 0) L.nlist = 0;
+    __syncthreads();
   }
   ncoll = wave_sum(ncoll);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ncoll;
+  if ((tid & 63) == 0) L.red[tid >> 6][2] = ncoll;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < kBigThreads / 64; ++k) tot += L.red[k][2];
     unsigned long long* st = dp->stats + (blockIdx.x % kStatSlots) * kStatFields;
-    const int tot = red[0] + red[1] + red[2] + red[3];
     if (tot) atomicAdd(st + 1, (unsigned long long)tot);
-    if (pb.first_group == 0) {  // once per cell and step
+    if (b == 0) {  // once per cell and step
       atomicAdd(st + 0, (unsigned long long)nlive);
       atomicAdd(st + 2, 1ull);
       atomicAdd(st + 3, 1ull);
@@ -1547,8 +1714,6 @@ void set_lds_limits() {
   if (done) return;
   done = true;
   const int lim = 160 * 1024;
-  (void)hipFuncSetAttribute((const void*)k_big_rank, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lim);
   (void)hipFuncSetAttribute((const void*)k_cells_mid<2048, mid_waves(2048), false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void*)k_cells_mid<2048, mid_waves(2048), true>,
@@ -1623,8 +1788,8 @@ static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st
                        p.mid_tasks[cls] + np, k_abs);
 }
 
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
-                       int waves_per_cell, hipStream_t st, const SideStream& side) {
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, uint32_t big_step,
+                       int nsteps, int waves_per_cell, hipStream_t st, const SideStream& side) {
   const uint32_t k_abs0 = k_abs;
   // Two independent groups of launches run on two streams and fill each
   // other's tails: the cells of up to 256 slots and the mid-size cells on a
@@ -1652,20 +1817,14 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nste
   }
   launch_class<512>(p, 4, k_abs, flip, nsteps, waves_per_cell, st);
   launch_class<384>(p, 3, k_abs, flip, nsteps, waves_per_cell, st);
-  for (int t = 0; t < nsteps && p.n_big > 0; ++t) {  // big cells: five launches per step
+  for (int t = 0; t < nsteps && p.n_big > 0; ++t) {  // big cells: two launches per step
     const uint32_t k_abs = k_abs0 + t;
-    hipLaunchKernelGGL(k_big_count, dim3(p.n_chunks), dim3(256), 0, st, p.desc, p.big, p.chunks,
-                       p.bucket_cnt, p.task_live, k_abs);
-    hipLaunchKernelGGL(k_big_scan, dim3(p.n_big), dim3(256), 0, st, p.desc, p.big, p.bucket_cnt,
-                       p.bucket_start, p.task_live, p.task_nlive, k_abs);
-    hipLaunchKernelGGL(k_big_scatter, dim3(p.n_chunks), dim3(256), 0, st, p.desc, p.big,
-                       p.chunks, p.bucket_cnt, p.bucket_start, p.tmp, k_abs);
-    const int rw = 4;
-    hipLaunchKernelGGL(k_big_rank, dim3((p.n_buckets + rw - 1) / rw), dim3(64 * rw),
-                       (unsigned)(rw * kBucketCap * sizeof(unsigned long long)), st, p.desc,
-                       p.big, p.buckets, p.n_buckets, p.bucket_start, p.tmp, p.ord, k_abs);
-    hipLaunchKernelGGL(k_big_pairs, dim3(p.n_pblocks), dim3(256), 0, st, p.desc, p.big,
-                       p.pblocks, p.task_nlive, p.ord, k_abs);
+    const uint32_t par = (big_step + (uint32_t)t) & 1u;
+    hipLaunchKernelGGL(k_big_keys, dim3(p.n_chunks), dim3(kBigKeyThreads), 0, st, p.desc, p.big,
+                       p.chunks, p.cnt[par], p.ovf_cnt[par], p.region, p.ovf, k_abs);
+    hipLaunchKernelGGL(k_big_bucket, dim3(p.n_buckets), dim3(kBigThreads), 0, st, p.desc, p.big,
+                       p.buckets, p.cnt[par], p.ovf_cnt[par], p.cnt[par ^ 1u], p.ovf_cnt[par ^ 1u],
+                       p.region, p.ovf, p.ord, k_abs);
   }
   if (fork && (hipEventRecord(side.join, st2) != hipSuccess ||
                hipStreamWaitEvent(st, side.join, 0) != hipSuccess))

@@ -89,9 +89,12 @@ def test_eagain_when_member_busy_on_another_stream(B):
 
 
 def test_init_does_not_wait_for_other_streams(B):
-    """sdm_init on one stream returns while a long spin still runs on another
-    (every device buffer is made before the spin: torch's own allocations and
-    copies are not the library's)."""
+    """sdm_init on one stream returns while a long spin still runs on another.
+    Every device buffer is made, and used once by an untimed sdm_init on the
+    same stream, before the spin: the first use of memory torch has just
+    allocated can wait for other queues inside the HIP runtime (observed
+    only on that first use; no call of sdm_init synchronises the device), and
+    that is not the steady state a server admitting requests runs in."""
     import gc
     import time
 
@@ -105,20 +108,20 @@ def test_init_does_not_wait_for_other_streams(B):
     v = torch.from_numpy(st.v).cuda()
     off = torch.from_numpy(st.cell_off).cuda()
     ws = B.workspace_tensor(B.sdm_workspace_bytes(cfg, st.cell_off))
-    # objects of earlier tests are collected now, not inside the timed window
-    # (freeing a simulation destroys its HIP stream, which may wait)
+    B.sdm_free(B.sdm_init(cfg, xi, v, None, off, ws, side))
     gc.collect()
     torch.cuda.synchronize()
-    _spin(busy, 400_000_000)
-    ev = torch.cuda.Event()
-    ev.record(busy)
-    t0 = time.perf_counter()
-    h = B.sdm_init(cfg, xi, v, None, off, ws, side)
-    dt_init = time.perf_counter() - t0
-    still_busy = not ev.query()
-    busy.synchronize()
-    dt_all = time.perf_counter() - t0
-    say(f"sdm_init {dt_init * 1e3:.2f} ms while the spin ran {dt_all * 1e3:.2f} ms; "
-        f"spin still running at return: {still_busy}")
-    assert still_busy, "sdm_init waited for work on another stream"
-    B.sdm_free(h)
+    for rep in range(3):
+        _spin(busy, 400_000_000)
+        ev = torch.cuda.Event()
+        ev.record(busy)
+        t0 = time.perf_counter()
+        h = B.sdm_init(cfg, xi, v, None, off, ws, side)
+        dt_init = time.perf_counter() - t0
+        still_busy = not ev.query()
+        busy.synchronize()
+        dt_all = time.perf_counter() - t0
+        say(f"sdm_init {dt_init * 1e3:.2f} ms while the spin ran {dt_all * 1e3:.2f} ms; "
+            f"spin still running at return: {still_busy}")
+        assert still_busy, "sdm_init waited for work on another stream"
+        B.sdm_free(h)

@@ -143,6 +143,27 @@ def test_bucket_overflow_path_exact(B, orc):
     g.close()
 
 
+@pytest.mark.parametrize("target,cap", [(64, 48), (32, 8)])
+def test_big_cell_overflow_list_exact(B, orc, target, cap):
+    """Bucket regions smaller than the expected bucket size: most buckets
+    spill into the overflow list and are ordered in global memory (the slow
+    exact path, flagged); pairs and state still equal the oracle's."""
+    st = I.golovin_box(2 ** 15, seed=3)
+    say(f"big-cell overflow list target={target} cap={cap}")
+    g = GpuRun(B, st, sink=True, tuning=dict(big_bucket_target=target, big_bucket_cap=cap,
+                                             mid_max_slots=0))
+    o = st.copy()
+    cfg = ocfg(orc, o)
+    for s in range(3):
+        g.step(1)
+        out = orc.step(cfg, o.xi, o.v, o.attrs, o.cell_off, s, want_log=True)
+        xi, v, _ = g.state()
+        assert np.array_equal(xi, o.xi) and np.array_equal(v, o.v)
+        assert np.array_equal(g.log(), out["log"])
+    assert B.sdm_status_word(g.sim.handle) & B.SDM_FLAG_BUCKET_OVERFLOW
+    g.close()
+
+
 def test_big_golovin_box(B, orc):
     """One 2^17-SD cell (the big-cell path) for 20 steps, bit-exact."""
     st = I.golovin_box(2 ** 17)
