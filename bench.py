@@ -61,11 +61,13 @@ def make_state(name):
 
 
 def kernel_source_sha():
-    h = hashlib.sha256()
-    for f in ("sdm_kernels.hip", "sdm_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2103_17238_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the source the workgroup-per-cell kernel is built from: the
+    kernel file up to its mid-size section (the generator, the collision
+    kernels, the wave helpers, the cell kernel itself).  Committed traffic
+    figures are used only while it matches."""
+    with open(os.path.join(ROOT, "paper_2103_17238_amd", "csrc", "sdm_kernels.hip")) as fh:
+        src = fh.read()
+    return hashlib.sha256(src[: src.index("// Mid-size cells")].encode()).hexdigest()[:16]
 
 
 def displace_source_sha():
@@ -119,6 +121,42 @@ def traffic_from_profiles(kernel_name, workload, launches_bytes, tuning=None):
         return None
     # KiB per step, already scaled by the copy probe (see the json's commands)
     return (shape["fetch_kib_per_step"] + shape["write_kib_per_step"]) * 1024.0
+
+
+# VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
+# every 4 cycles (16 lanes per cycle), 2.4 GHz
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+
+
+def valu_from_profiles(tuning, substeps_per_cell_step, step_s):
+    """VALU issue of the step from the committed SQ-counter summary of the same
+    cell-kernel source and launch shape: instructions per step (the profiled
+    count scaled by the substeps per cell-step of this run over the profiled
+    run's) over the measured step time, against the issue ceiling; None if
+    the summary does not match."""
+    path = os.path.join(PROFILES, "k_cells_grid256_sq.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_source_sha() or tuning is None:
+        return None
+    if d.get("shape") != f"{tuning['wave_class_mask']:#x}/{tuning['waves_per_cell']}":
+        return None
+    insts = sum(k["SQ_INSTS_VALU"] for k in d["kernels"].values())
+    waves = sum(k["SQ_WAVES"] for k in d["kernels"].values())
+    lanes = sum(k["SQ_THREAD_CYCLES_VALU"] for k in d["kernels"].values()) / insts
+    scale = substeps_per_cell_step / d["substeps_per_cell_step"]
+    per_step = insts * scale
+    achieved = per_step / step_s
+    return {"bound": "valu-issue", "unit": "wave64 VALU instructions/s",
+            "insts_per_step": per_step, "insts_per_cell_step": per_step / waves,
+            "achieved": achieved, "peak": VALU_PEAK_WAVE_INSTS,
+            "frac": achieved / VALU_PEAK_WAVE_INSTS, "lanes_active": lanes,
+            "note": "counts from the committed rocprofv3 SQ summary of this kernel source and "
+                    "shape, scaled by substeps per cell-step (profiled "
+                    f"{d['substeps_per_cell_step']:.3f}); peak = 256 CUs x 4 SIMDs x 2.4 GHz "
+                    "/ 4 cycles per wave64 instruction"}
 
 
 def cpu_baseline(state, n_cells_sample, steps):
@@ -442,6 +480,9 @@ def main():
         kernel_name = " || ".join(f"k_cells<{c},{tuning['waves_per_cell']},{mode}>" for c in caps)
     achieved = alg_bytes / K / (per_launch_ms.mean() / 1e3) / 1e9
     traffic = traffic_from_profiles("k_cells", args.workload, alg_bytes / K, tuning)
+    subs = stats["cell_substeps"] / max(stats["cell_steps"], 1)
+    valu = (valu_from_profiles(tuning, subs, per_launch_ms.mean() / 1e3)
+            if args.workload == "grid256" else None)
     line = {
         "metric": METRIC,
         "value": value,
@@ -481,6 +522,7 @@ def main():
             "copy_gbs": copy_gbs,
             "frac_of_copy": achieved / copy_gbs,
         },
+        "valu": valu,
         "stats": {"live_sd_steps": live, "colliding_pairs": coll,
                   "cell_substeps": stats["cell_substeps"], "cell_steps": stats["cell_steps"],
                   # the adaptive load the timed steps carried (it grows as drops

@@ -59,7 +59,10 @@
  * (sdm_debug_gamma_sink, sdm_batch_workspace_bytes,
  * sdm_autotune_scratch_bytes) are host-only, except right after a
  * device-side sdm_rebind, when they first copy the new offsets to the host
- * with a blocking copy.
+ * with a blocking copy.  The HIP runtime maps streams onto a few hardware
+ * queues (GPU_MAX_HW_QUEUES, 4 by default); streams that share a queue run
+ * in order, so synchronising `stream` then also waits for work enqueued
+ * earlier on the streams it shares a queue with.
  */
 #ifndef SDM_H
 #define SDM_H
@@ -142,15 +145,18 @@ size_t sdm_workspace_bytes(const sdm_config* cfg, const int64_t* host_cell_off);
  * and validates the state (one kernel), all ordered on `stream`, which it
  * synchronises (twice; work on other streams keeps running).  The step
  * counter starts at 0.
- * Returns SDM_EINVAL for a bad cfg/state (also: adaptive mode with a cell of
- * more than 16384 slots), SDM_ENOMEM if the workspace is too small.
+ * Returns SDM_EINVAL for a bad cfg/state, SDM_ENOMEM if the workspace is
+ * too small.
  */
 sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v, double* attrs,
                     const int64_t* cell_off, void* workspace, size_t workspace_bytes,
                     void* stream);
 
-/* Advance n_steps >= 0 outer steps (enqueue only). Steps beyond the step limit are skipped.
- * SDM_EAGAIN: the simulation's last steps were enqueued on another stream and still run. */
+/* Advance n_steps >= 0 outer steps (enqueue only, except below). Steps beyond the step limit
+ * are skipped.  SDM_EAGAIN: the simulation's last steps were enqueued on another stream and
+ * still run.  Adaptive mode with cells on the big-cell path (above the mid-size limit): the
+ * number of substeps is found on the device, so the call synchronises `stream` once every
+ * 4 substep rounds of each step. */
 sdm_status sdm_coalescence_step(sdm_sim* s, int32_t n_steps, void* stream);
 
 /*

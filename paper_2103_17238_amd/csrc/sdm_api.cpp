@@ -24,7 +24,9 @@
 #include "sdm_internal.hpp"
 #include "sdm_refresh.hpp"
 
+using sdm::BigAdapt;
 using sdm::BigBucket;
+using sdm::BigPairBlock;
 using sdm::BigChunk;
 using sdm::BigTask;
 using sdm::PlanDev;
@@ -177,10 +179,13 @@ struct Tables {
   int n_plain[sdm::kNumClasses] = {};
   std::vector<sdm::CellTask> mid[sdm::kNumMid];  // plain-mode cells first, then adaptive
   int n_mid_plain[sdm::kNumMid] = {0, 0, 0, 0};
-  bool adaptive_big = false;  // an adaptive-mode cell fell to the big-cell path
   std::vector<BigTask> big;
-  std::vector<BigChunk> chunks;
+  std::vector<BigChunk> chunks;  // plain-mode big cells
   std::vector<BigBucket> buckets;
+  std::vector<int> abig;  // adaptive big cells: their tasks, chunks, buckets, pair blocks
+  std::vector<BigChunk> achunks;
+  std::vector<BigBucket> abuckets;
+  std::vector<BigPairBlock> apblocks;
   int64_t tmp_total = 0;     // slots of big cells (overflow and order entries)
   int64_t region_total = 0;  // bucket-region entries
   int64_t bucket_total = 0;
@@ -217,7 +222,6 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
         mids[k].push_back({n, i, c, ms[i]->cfg.adaptive});
         continue;
       }
-      if (ms[i]->cfg.adaptive) T.adaptive_big = true;
       BigTask t{};
       t.xi = ms[i]->xi + off[c];
       t.v = ms[i]->v + off[c];
@@ -234,8 +238,15 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
       T.bucket_total += t.nb;
       const int ti = (int)T.big.size();
       T.big.push_back(t);
-      for (int64_t f = 0; f < n; f += sdm::kChunk) T.chunks.push_back({ti, (int32_t)f});
-      for (int b = 0; b < t.nb; ++b) T.buckets.push_back({ti, b});
+      const bool ad = ms[i]->cfg.adaptive != 0;
+      for (int64_t f = 0; f < n; f += sdm::kChunk)
+        (ad ? T.achunks : T.chunks).push_back({ti, (int32_t)f});
+      for (int b = 0; b < t.nb; ++b) (ad ? T.abuckets : T.buckets).push_back({ti, b});
+      if (ad) {
+        T.abig.push_back(ti);
+        for (int64_t m = 0; m < n / 2; m += sdm::kAbigPairs)
+          T.apblocks.push_back({ti, (int32_t)m});
+      }
     }
   }
   // plain-mode cells first (one kernel each), largest first within a mode
@@ -265,7 +276,8 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
 struct Layout {
   size_t desc, wave[sdm::kNumClasses], wave_alt[sdm::kNumClasses], order_flag[sdm::kNumClasses],
       order_cnt[sdm::kNumClasses], mid[sdm::kNumMid], big, chunks, buckets, cnt[2], ovf_cnt[2],
-      region, ovf, ord, total;
+      region, ovf, ord, abig, achunks, abuckets, apblocks, astate[2], apmax[2], apre, apair,
+      aactive, total;
 };
 
 static Layout layout_of(int n_members, const Tables& T) {
@@ -296,6 +308,18 @@ static Layout layout_of(int n_members, const Tables& T) {
   L.region = take(sizeof(unsigned long long) * std::max<int64_t>(T.region_total, 1));
   L.ovf = take(sizeof(unsigned long long) * std::max<int64_t>(T.tmp_total, 1));
   L.ord = take(sizeof(uint32_t) * std::max<int64_t>(T.tmp_total, 1));
+  const bool ad = !T.abig.empty();
+  L.abig = take(sizeof(int) * std::max<size_t>(T.abig.size(), 1));
+  L.achunks = take(sizeof(BigChunk) * std::max<size_t>(T.achunks.size(), 1));
+  L.abuckets = take(sizeof(BigBucket) * std::max<size_t>(T.abuckets.size(), 1));
+  L.apblocks = take(sizeof(BigPairBlock) * std::max<size_t>(T.apblocks.size(), 1));
+  for (int k = 0; k < 2; ++k) {
+    L.astate[k] = take(sizeof(BigAdapt) * (ad ? T.big.size() : 1));
+    L.apmax[k] = take(sizeof(unsigned long long) * (ad ? T.big.size() : 1));
+  }
+  L.apre = take(sizeof(double) * (size_t)(ad ? T.tmp_total : 1));
+  L.apair = take(sizeof(unsigned long long) * (size_t)(ad ? T.tmp_total : 1));
+  L.aactive = take(sizeof(uint32_t));
   L.total = o;
   return L;
 }
@@ -334,6 +358,7 @@ struct Plan {
   uint32_t counter = 0;       // launch step of the next step
   uint32_t flip = 0;          // launches since the tables were built
   uint32_t big_steps = 0;     // big-cell steps launched since the tables were built
+  uint32_t abig_rounds = 0;   // adaptive big-cell substep rounds launched since then
   sdm::SideStream side;       // created at the first step
   std::shared_ptr<Busy> busy;  // event recorded after each step call, created at the first
   Plan() = default;
@@ -408,7 +433,6 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
     if (!fresh_offsets(m)) return SDM_EDEVICE;
   p->T = Tables();
   build_tables(p->members, p->tuning, p->T);
-  if (p->T.adaptive_big) return SDM_EINVAL;  // adaptive mode needs cells <= mid_max_slots
   for (int k = 0; k < sdm::kNumClasses; ++k)  // every used class must fit one workgroup's LDS
     if (!p->T.wave[k].empty() && sdm::cell_lds_bytes(k) > lds_block_limit()) return SDM_EINVAL;
   for (int k = 0; k < sdm::kNumMid; ++k)
@@ -446,7 +470,23 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   d.region = reinterpret_cast<unsigned long long*>(w + L.region);
   d.ovf = reinterpret_cast<unsigned long long*>(w + L.ovf);
   d.ord = reinterpret_cast<uint32_t*>(w + L.ord);
+  d.abig = reinterpret_cast<const int*>(w + L.abig);
+  d.n_abig = (int)p->T.abig.size();
+  d.achunks = reinterpret_cast<const BigChunk*>(w + L.achunks);
+  d.n_achunks = (int)p->T.achunks.size();
+  d.abuckets = reinterpret_cast<const BigBucket*>(w + L.abuckets);
+  d.n_abuckets = (int)p->T.abuckets.size();
+  d.apblocks = reinterpret_cast<const BigPairBlock*>(w + L.apblocks);
+  d.n_apblocks = (int)p->T.apblocks.size();
+  for (int k = 0; k < 2; ++k) {
+    d.astate[k] = reinterpret_cast<BigAdapt*>(w + L.astate[k]);
+    d.apmax[k] = reinterpret_cast<unsigned long long*>(w + L.apmax[k]);
+  }
+  d.apre = reinterpret_cast<double*>(w + L.apre);
+  d.apair = reinterpret_cast<unsigned long long*>(w + L.apair);
+  d.aactive = reinterpret_cast<uint32_t*>(w + L.aactive);
   p->big_steps = 0;
+  p->abig_rounds = 0;
 
   // the old tables may still be read by steps enqueued on `st`
   HIP_TRY(hipStreamSynchronize(st));
@@ -466,6 +506,10 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   HIP_TRY(upload(const_cast<BigTask*>(d.big), p->T.big, st));
   HIP_TRY(upload(const_cast<BigChunk*>(d.chunks), p->T.chunks, st));
   HIP_TRY(upload(const_cast<BigBucket*>(d.buckets), p->T.buckets, st));
+  HIP_TRY(upload(const_cast<int*>(d.abig), p->T.abig, st));
+  HIP_TRY(upload(const_cast<BigChunk*>(d.achunks), p->T.achunks, st));
+  HIP_TRY(upload(const_cast<BigBucket*>(d.abuckets), p->T.abuckets, st));
+  HIP_TRY(upload(const_cast<BigPairBlock*>(d.apblocks), p->T.apblocks, st));
   for (int k = 0; k < 2 && !p->T.big.empty(); ++k) {  // both sets of counters start at zero
     HIP_TRY(hipMemsetAsync(d.cnt[k], 0, sizeof(uint32_t) * p->T.bucket_total, st));
     HIP_TRY(hipMemsetAsync(d.ovf_cnt[k], 0, sizeof(uint32_t) * p->T.big.size(), st));
@@ -488,6 +532,30 @@ static sdm_status plan_refresh(Plan* p, hipStream_t st) {
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(upload(const_cast<SimDesc*>(p->dev.desc), p->desc, st));
   HIP_TRY(hipStreamSynchronize(st));
+  return SDM_OK;
+}
+
+// One outer step of the plan's adaptive big cells: substep rounds until every
+// cell is done, reading the count of cells still stepping every
+// kAbigRoundsPerCheck rounds (a synchronisation of `st`).
+static sdm_status abig_step(Plan* p, uint32_t k_abs, hipStream_t st) {
+  uint32_t umax = 0;
+  for (auto* m : p->members)
+    if (m->cfg.adaptive)
+      umax = std::max<uint32_t>(umax, (uint32_t)(m->cfg.max_substeps > 0 ? m->cfg.max_substeps
+                                                                         : 1024));
+  if (sdm::launch_abig_init(p->dev, k_abs, st) != hipSuccess) return SDM_EDEVICE;
+  // a capped substep ends a cell's step: umax + 1 rounds always suffice
+  for (uint32_t r = 0; r <= umax;) {
+    for (int i = 0; i < sdm::kAbigRoundsPerCheck && r <= umax; ++i, ++r)
+      if (sdm::launch_abig_round(p->dev, k_abs, r, p->abig_rounds++, st) != hipSuccess)
+        return SDM_EDEVICE;
+    uint32_t active = 0;
+    if (sdm::launch_abig_active(p->dev, r, p->dev.aactive, st) != hipSuccess ||
+        !read_back(&active, p->dev.aactive, sizeof(uint32_t), st))
+      return SDM_EDEVICE;
+    if (active == 0) break;
+  }
   return SDM_OK;
 }
 
@@ -531,6 +599,10 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
                          p->tuning.waves_per_cell, st, p->side) != hipSuccess)
       return SDM_EDEVICE;
     p->big_steps += (uint32_t)f;
+    for (int t = 0; t < f && p->dev.n_abig > 0; ++t) {  // adaptive big cells: substep rounds
+      const sdm_status r2 = abig_step(p, p->counter + (uint32_t)(k + t), st);
+      if (r2 != SDM_OK) return r2;
+    }
     k += f;
   }
   p->counter += (uint32_t)n_steps;
@@ -621,6 +693,20 @@ static size_t plan_bytes_bound(const sdm_config* c) {
   take(sizeof(unsigned long long) * (size_t)(2 * ns + kBigRegionSlack * nbig + 1));
   take(sizeof(unsigned long long) * (size_t)std::max<int64_t>(ns, 1));
   take(sizeof(uint32_t) * (size_t)std::max<int64_t>(ns, 1));
+  // adaptive big cells: task list, chunks and buckets (counted above once),
+  // pair blocks, per-cell state and largest p, per-pair pre-products and slots
+  const bool ad = c->adaptive != 0;
+  take(sizeof(int) * (size_t)std::max<int64_t>(nbig, 1));
+  take(sizeof(BigChunk) * (size_t)(ad ? ns / sdm::kChunk + nbig + 1 : 1));
+  take(sizeof(BigBucket) * (size_t)(ad ? nbk : 1));
+  take(sizeof(BigPairBlock) * (size_t)(ad ? ns / (2 * sdm::kAbigPairs) + nbig + 1 : 1));
+  for (int k = 0; k < 2; ++k) {
+    take(sizeof(BigAdapt) * (size_t)std::max<int64_t>(nbig, 1));
+    take(sizeof(unsigned long long) * (size_t)std::max<int64_t>(nbig, 1));
+  }
+  take(sizeof(double) * (size_t)(ad ? std::max<int64_t>(ns, 1) : 1));
+  take(sizeof(unsigned long long) * (size_t)(ad ? std::max<int64_t>(ns, 1) : 1));
+  take(sizeof(uint32_t));
   (void)T;
   return o;
 }
@@ -665,13 +751,6 @@ sdm_status sdm_init(sdm_sim** out, const sdm_config* cfg, int64_t* xi, double* v
   if (!offsets_ok(cfg, s->off.data())) {
     delete s;
     return SDM_EINVAL;
-  }
-  if (cfg->adaptive) {
-    for (int c = 0; c < cfg->n_cells; ++c)
-      if (s->off[c + 1] - s->off[c] > sdm::kMidCapMax) {
-        delete s;
-        return SDM_EINVAL;
-      }
   }
   const size_t need = sim_region_bytes(cfg->n_cells) + plan_bytes_for(cfg, s->off.data());
   if (workspace_bytes < need) {
@@ -903,9 +982,6 @@ static sdm_status rebind_host(sdm_sim* s, int64_t* xi, double* v, double* attrs,
     return SDM_EDEVICE;
   }
   if (!offsets_ok(&cfg, off.data())) return SDM_EINVAL;
-  if (cfg.adaptive)
-    for (int c = 0; c < cfg.n_cells; ++c)
-      if (off[c + 1] - off[c] > sdm::kMidCapMax) return SDM_EINVAL;
   if (s->ws_bytes < sim_region_bytes(cfg.n_cells) + plan_bytes_for(&cfg, off.data()))
     return SDM_ENOMEM;
   std::vector<int64_t> pb((size_t)cfg.n_cells + 1, 0);

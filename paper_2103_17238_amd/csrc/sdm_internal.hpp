@@ -14,6 +14,8 @@ constexpr int kWaveCapMax = 512;  // cells above this go to the mid-size or big-
 constexpr int kNumMid = 4;        // mid-size capacities 2048, 4096, 8192, 16384 slots
 constexpr int kMidCapMax = 16384;
 constexpr int kChunk = 4096;      // slots per block of the big-cell key pass
+constexpr int kAbigPairs = 256;   // pairs per block of the adaptive big-cell pair pass
+constexpr int kAbigRoundsPerCheck = 4;  // adaptive big-cell substep rounds between host checks
 constexpr int kMinBucketTarget = 32;
 constexpr int kOrderBlock = 1024;  // tasks per block of the dispatch-order partition
 constexpr int kOrderGroups = 4;    // dispatch-order groups by substeps taken
@@ -90,6 +92,20 @@ struct BigBucket {  // one bucket of one big cell
   int32_t bucket;
 };
 
+struct BigPairBlock {  // consecutive pairs of one adaptive big cell
+  int32_t task;
+  int32_t first;
+};
+
+// An adaptive big cell within one outer step (two copies alternate by round).
+struct BigAdapt {
+  double dt_left;  // time left in the step [s]
+  uint32_t u;      // substeps taken
+  uint32_t done;   // 1: nothing left to do in this step
+  int32_t nlive;   // live SDs at the start of the substep (set by the pre-product pass)
+  uint32_t pad;
+};
+
 // Device view of a launch plan (all pointers carved from a workspace).
 struct PlanDev {
   const SimDesc* desc;
@@ -120,6 +136,22 @@ struct PlanDev {
   unsigned long long* region;  // bucket regions
   unsigned long long* ovf;     // overflow entries (a full bucket's extra entries)
   uint32_t* ord;               // order of a bucket ranked in global memory
+  // adaptive big cells: their tasks, key chunks, buckets and pair blocks;
+  // per-cell state and largest p (two copies alternating by round); per
+  // pair pre-products and slots
+  const int* abig;
+  int n_abig;
+  const BigChunk* achunks;
+  int n_achunks;
+  const BigBucket* abuckets;
+  int n_abuckets;
+  const BigPairBlock* apblocks;
+  int n_apblocks;
+  BigAdapt* astate[2];
+  unsigned long long* apmax[2];
+  double* apre;
+  unsigned long long* apair;
+  uint32_t* aactive;  // device word: cells still stepping
 };
 
 // second stream (and fork/join events) for concurrent class launches
@@ -137,6 +169,13 @@ struct SideStream {
 // set of bucket counters).
 hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, uint32_t big_step,
                        int nsteps, int waves_per_cell, hipStream_t st, const SideStream& side);
+// Adaptive big cells: the start of an outer step (every cell's state
+// reset), one substep round (keys, order and pre-products, pairs), and the
+// count of cells still stepping after a round, into a device word.
+hipError_t launch_abig_init(const PlanDev& p, uint32_t k_abs, hipStream_t st);
+hipError_t launch_abig_round(const PlanDev& p, uint32_t k_abs, uint32_t round, uint32_t cnt_par,
+                             hipStream_t st);
+hipError_t launch_abig_active(const PlanDev& p, uint32_t round, uint32_t* count, hipStream_t st);
 hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
                           double* attr_sums, const double* edges, int n_bins, double* spectrum,
                           hipStream_t st);

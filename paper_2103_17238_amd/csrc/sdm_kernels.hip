@@ -1143,13 +1143,20 @@ __global__ void __launch_bounds__(kBigKeyThreads) k_big_keys(
     const SimDesc* __restrict__ descs, const BigTask* __restrict__ big,
     const BigChunk* __restrict__ chunks, uint32_t* __restrict__ cnt,
     uint32_t* __restrict__ ovf_cnt, unsigned long long* __restrict__ region,
-    unsigned long long* __restrict__ ovf, uint32_t k_abs) {
+    unsigned long long* __restrict__ ovf, uint32_t k_abs,
+    const BigAdapt* __restrict__ astate) {
   __shared__ uint32_t hist[kBigKeyLdsBuckets];
   const BigChunk ch = chunks[blockIdx.x];
   const BigTask tk = big[ch.task];
   const SimDesc* dp = descs + tk.sim;
   const uint32_t s = k_abs + dp->step_delta;
   if (s >= dp->step_limit) return;
+  uint32_t u = 0;  // substep (adaptive cells: this round's, from the cell's state)
+  if (astate) {
+    const BigAdapt as = astate[ch.task];
+    if (as.done) return;
+    u = as.u;
+  }
   const uint32_t nb = (uint32_t)tk.nb;
   const bool local = nb <= (uint32_t)kBigKeyLdsBuckets;
   if (local) {
@@ -1167,7 +1174,7 @@ __global__ void __launch_bounds__(kBigKeyThreads) k_big_keys(
     long long xv[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) xv[e] = j0 + e < tk.n_slots ? tk.xi[j0 + e] : 0;
-    const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)tk.cell, s, 0u), dp->seed_lo,
+    const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)tk.cell, s, 2u * u), dp->seed_lo,
                            dp->seed_hi);
     kk[r][0] = w.x;
     kk[r][1] = w.y;
@@ -1295,12 +1302,18 @@ __device__ unsigned long long bucket_min(const BigTask& tk, const uint32_t* cnt,
   return r;
 }
 
+// ADAPT: the first pass of an adaptive substep; instead of drawing the
+// collisions it stores every pair's slots and pre-product (max xi K) S and
+// raises the cell's largest p at the remaining time (k_abig_pairs draws).
+template <bool ADAPT>
 __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
     const SimDesc* __restrict__ descs, const BigTask* __restrict__ big,
     const BigBucket* __restrict__ buckets, uint32_t* __restrict__ cnt,
     uint32_t* __restrict__ ovf_cnt, uint32_t* __restrict__ cnt_next,
     uint32_t* __restrict__ ovf_cnt_next, const unsigned long long* __restrict__ region,
-    const unsigned long long* __restrict__ ovf, uint32_t* __restrict__ gord, uint32_t k_abs) {
+    const unsigned long long* __restrict__ ovf, uint32_t* __restrict__ gord, uint32_t k_abs,
+    BigAdapt* __restrict__ astate, unsigned long long* __restrict__ apmax,
+    double* __restrict__ apre, unsigned long long* __restrict__ apair) {
   __shared__ BigLds L;
   const int tid = threadIdx.x;
   const BigBucket bk = buckets[blockIdx.x];
@@ -1314,6 +1327,12 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
   const SimDesc* dp = descs + tk.sim;
   const uint32_t s = k_abs + dp->step_delta;
   if (s >= dp->step_limit) return;
+  double q_left = 0.0;
+  if (ADAPT) {
+    const BigAdapt as = astate[bk.task];
+    if (as.done) return;
+    q_left = as.dt_left / dp->dv;
+  }
   const int nb = tk.nb;
   // this bucket's start and the cell's live count
   int before = 0, total = 0;
@@ -1327,7 +1346,8 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
   const int len = (int)cnt[tk.bucket_base + b];
   const int P = nlive >> 1;
   const int c = tk.cell;
-  int64_t* sink = dp->sink;
+  if (ADAPT && b == 0 && tid == 0) astate[bk.task].nlive = nlive;
+  int64_t* sink = ADAPT ? nullptr : dp->sink;
   const int64_t sink_base = sink ? 2 * dp->pair_base[c] : 0;
   if (sink && b == 0)  // unused pair entries of the cell
     for (int m = P + tid; m < (tk.n_slots >> 1); m += kBigThreads) {
@@ -1433,6 +1453,35 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
   double* v = tk.v;
   const int64_t o0 = tk.xi - dp->xi;
   const int npairs = any_pair ? min((len - i0 + 1) >> 1, P - ((start + i0) >> 1)) : 0;
+  if (ADAPT) {  // pre-products, pairs and this bucket's largest p at the remaining time
+    double pm = 0.0;
+    for (int t = tid; t < npairs; t += kBigThreads) {
+      const int i = i0 + 2 * t;
+      const int m = (start + i) >> 1;
+      const int a = (int)(fast ? L.ord[i] : gsorted[i]);
+      const int bb = (int)(i + 1 < len ? (fast ? L.ord[i + 1] : gsorted[i + 1]) : L.next_slot);
+      const long long xa = xi[a], xb = xi[bb];
+      const double kv = coal_kernel(dp->kernel, dp->b, v[a], v[bb]);
+      const double pp = ((double)(xa > xb ? xa : xb) * kv) * S;
+      apre[tk.tmp_base + m] = pp;
+      apair[tk.tmp_base + m] = (unsigned long long)(uint32_t)a | ((unsigned long long)bb << 32);
+      pm = fmax(pm, pp * q_left);
+    }
+    // largest p of the block; p >= 0, so its bits order like the values
+    const int lane = tid & 63, wv = tid >> 6;
+    unsigned long long pb = (unsigned long long)__double_as_longlong(pm);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) pb = max(pb, (unsigned long long)__shfl_xor(pb, o));
+    if (lane == 0) L.red64[wv] = pb;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long r = 0;
+#pragma unroll
+      for (int k = 0; k < kBigThreads / 64; ++k) r = max(r, L.red64[k]);
+      if (r) atomicMax(&apmax[bk.task], r);
+    }
+    return;
+  }
   for (int base = 0; base < npairs; base += kBigThreads) {
     const int t = base + tid;
     if (t < npairs) {
@@ -1508,6 +1557,178 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
       atomicAdd(st + 3, 1ull);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive substeps of big cells.  One outer step of the adaptive big cells
+// is a sequence of rounds, each one substep of every cell not yet done:
+// k_big_keys (keys of substep u), k_big_bucket<true> (order, pairs,
+// pre-products, the cell's largest p at the remaining time dt_left) and
+// k_abig_pairs (the substep length dt_left / pmax, or dt_left when pmax <= 1
+// or the substep cap is reached; p at the substep clamped to 1 unless
+// capped; gamma; updates; the cell's next state).  A cell's state has two
+// copies: round r reads copy r mod 2 and writes the other (a cell already done
+// copies its state over unchanged).
+// ---------------------------------------------------------------------------
+__global__ void k_abig_init(const SimDesc* __restrict__ descs, const BigTask* __restrict__ big,
+                            const int* __restrict__ atask, int n, BigAdapt* __restrict__ st0,
+                            unsigned long long* __restrict__ pm0,
+                            unsigned long long* __restrict__ pm1, uint32_t k_abs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t = atask[i];
+  const SimDesc* dp = descs + big[t].sim;
+  BigAdapt a;
+  a.dt_left = dp->dt;
+  a.u = 0;
+  a.done = (k_abs + dp->step_delta >= dp->step_limit) ? 1u : 0u;
+  a.nlive = 0;
+  a.pad = 0;
+  st0[t] = a;
+  pm0[t] = 0;
+  pm1[t] = 0;
+}
+
+__global__ void __launch_bounds__(kAbigPairs) k_abig_pairs(
+    const SimDesc* __restrict__ descs, const BigTask* __restrict__ big,
+    const BigPairBlock* __restrict__ pblocks, const BigAdapt* __restrict__ cur,
+    BigAdapt* __restrict__ nxt, const unsigned long long* __restrict__ pm_cur,
+    unsigned long long* __restrict__ pm_nxt, const double* __restrict__ apre,
+    const unsigned long long* __restrict__ apair, uint32_t k_abs) {
+  __shared__ uint32_t lj[kAbigPairs], lk[kAbigPairs], lsplit[kAbigPairs];
+  __shared__ long long lg[kAbigPairs];
+  __shared__ int nlist, red[kAbigPairs / 64];
+  const int tid = threadIdx.x;
+  const BigPairBlock pb = pblocks[blockIdx.x];
+  const BigTask tk = big[pb.task];
+  const BigAdapt as = cur[pb.task];
+  if (as.done) {  // carried into the other copy, which the next round reads
+    if (pb.first == 0 && tid == 0) {
+      nxt[pb.task] = as;
+      pm_nxt[pb.task] = 0;
+    }
+    return;
+  }
+  const SimDesc* dp = descs + tk.sim;
+  const uint32_t s = k_abs + dp->step_delta;
+  const uint32_t u = as.u;
+  const bool capped = u >= (uint32_t)dp->max_substeps;
+  if (capped && tid == 0 && pb.first == 0) atomicOr(dp->status, kFlagSubstepCap);
+  const int nlive = as.nlive;
+  const int P = nlive >> 1;
+  const int c = tk.cell;
+  const int m = pb.first + tid;
+  int64_t* sink = dp->sink;
+  const int64_t sink_base = sink ? 2 * dp->pair_base[c] : 0;
+  if (tid == 0) nlist = 0;
+  __syncthreads();
+  double dt_sub = as.dt_left;
+  int ncoll = 0;
+  if (nlive >= 2) {
+    const double pmax = __longlong_as_double((long long)pm_cur[pb.task]);
+    dt_sub = (capped || pmax <= 1.0) ? as.dt_left : as.dt_left / pmax;
+    const double q = dt_sub / dp->dv;
+    if (m < P) {
+      const unsigned long long pr = apair[tk.tmp_base + m];
+      const int a = (int)(uint32_t)(pr & 0xFFFFFFFFull), bb = (int)(uint32_t)(pr >> 32);
+      double p = apre[tk.tmp_base + m] * q;
+      if (!capped && p > 1.0) p = 1.0;
+      const uint4 w = philox(make_uint4((uint32_t)(m >> 1), (uint32_t)c, s, 2u * u + 1u),
+                             dp->seed_lo, dp->seed_hi);
+      const double phi = (m & 1) == 0 ? uniform53(w.x, w.y) : uniform53(w.z, w.w);
+      const long long gamma = collisions(p, phi, dp->status);
+      if (sink) {
+        sink[sink_base + 2 * m] = (int64_t)((uint64_t)a | ((uint64_t)bb << 32));
+        sink[sink_base + 2 * m + 1] = gamma;
+      }
+      if (gamma > 0) {
+        ++ncoll;
+        int64_t* xi = tk.xi;
+        const long long xa = xi[a], xb = xi[bb];
+        const bool a_is_j = xa >= xb;  // ties: the pair's first member
+        const long long xj = a_is_j ? xa : xb, xk = a_is_j ? xb : xa;
+        long long g = gamma;
+        if (g > 1) {
+          const long long ratio = xj / xk;
+          g = g < ratio ? g : ratio;
+        }
+        const int j = a_is_j ? a : bb, k = a_is_j ? bb : a;
+        const long long rest = xj - g * xk;
+        uint32_t split = 0;
+        if (rest > 0) {
+          xi[j] = rest;
+        } else {  // equal-multiplicity split
+          const long long h = xk >> 1;
+          xi[j] = h;
+          xi[k] = xk - h;
+          split = 1;
+        }
+        const int at = atomicAdd(&nlist, 1);
+        lj[at] = (uint32_t)j;
+        lk[at] = (uint32_t)k;
+        lsplit[at] = split;
+        lg[at] = g;
+      }
+    }
+  }
+  if (sink && m >= P && m < (tk.n_slots >> 1)) {  // no pair this substep
+    sink[sink_base + 2 * m] = -1;
+    sink[sink_base + 2 * m + 1] = -1;
+  }
+  __syncthreads();
+  {  // volumes and attributes of the listed pairs: one round of loads
+    const int nl = nlist;
+    const int F = 1 + dp->n_attr;
+    const int64_t o0 = tk.xi - dp->xi;
+    for (int t = tid; t < nl * F; t += kAbigPairs) {
+      const int li = t / F, f = t - li * F;
+      const int j = (int)lj[li], k = (int)lk[li];
+      double* X = f == 0 ? tk.v : dp->attrs + (int64_t)(f - 1) * dp->n_slots + o0;
+      const double val = fma((double)lg[li], X[j], X[k]);
+      X[k] = val;
+      if (lsplit[li]) X[j] = val;
+    }
+  }
+  ncoll = wave_sum(ncoll);
+  if ((tid & 63) == 0) red[tid >> 6] = ncoll;
+  __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < kAbigPairs / 64; ++k) tot += red[k];
+    unsigned long long* stt = dp->stats + (blockIdx.x % kStatSlots) * kStatFields;
+    if (tot) atomicAdd(stt + 1, (unsigned long long)tot);
+    if (pb.first == 0) {  // the cell's next state, once
+      BigAdapt na = as;
+      if (nlive < 2) {  // no pairs: the step ends here (a capped substep still counts)
+        na.u = u + (capped ? 1u : 0u);
+        na.done = 1;
+      } else {
+        na.dt_left = (dt_sub == as.dt_left) ? 0.0 : as.dt_left - dt_sub;
+        na.u = u + 1;
+        na.done = (na.dt_left > 0.0 && !capped) ? 0u : 1u;
+      }
+      nxt[pb.task] = na;
+      pm_nxt[pb.task] = 0;
+      if (u == 0) {
+        atomicAdd(stt + 0, (unsigned long long)nlive);
+        atomicAdd(stt + 3, 1ull);
+      }
+      if (na.u > u) atomicAdd(stt + 2, (unsigned long long)(na.u - u));
+    }
+  }
+}
+
+// adaptive big cells still stepping after a round: *count (host-read)
+__global__ void k_abig_active(const BigAdapt* __restrict__ st, const int* __restrict__ atask,
+                              int n, uint32_t* __restrict__ count) {
+  __shared__ int red[4];
+  int live = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) live += st[atask[i]].done ? 0 : 1;
+  live = wave_sum(live);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = live;
+  __syncthreads();
+  if (threadIdx.x == 0) *count = (uint32_t)(red[0] + red[1] + red[2] + red[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1817,18 +2038,51 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, uint32_t
   }
   launch_class<512>(p, 4, k_abs, flip, nsteps, waves_per_cell, st);
   launch_class<384>(p, 3, k_abs, flip, nsteps, waves_per_cell, st);
-  for (int t = 0; t < nsteps && p.n_big > 0; ++t) {  // big cells: two launches per step
+  for (int t = 0; t < nsteps && p.n_chunks > 0; ++t) {  // big cells: two launches per step
     const uint32_t k_abs = k_abs0 + t;
     const uint32_t par = (big_step + (uint32_t)t) & 1u;
     hipLaunchKernelGGL(k_big_keys, dim3(p.n_chunks), dim3(kBigKeyThreads), 0, st, p.desc, p.big,
-                       p.chunks, p.cnt[par], p.ovf_cnt[par], p.region, p.ovf, k_abs);
-    hipLaunchKernelGGL(k_big_bucket, dim3(p.n_buckets), dim3(kBigThreads), 0, st, p.desc, p.big,
-                       p.buckets, p.cnt[par], p.ovf_cnt[par], p.cnt[par ^ 1u], p.ovf_cnt[par ^ 1u],
-                       p.region, p.ovf, p.ord, k_abs);
+                       p.chunks, p.cnt[par], p.ovf_cnt[par], p.region, p.ovf, k_abs,
+                       (const BigAdapt*)nullptr);
+    hipLaunchKernelGGL(k_big_bucket<false>, dim3(p.n_buckets), dim3(kBigThreads), 0, st, p.desc,
+                       p.big, p.buckets, p.cnt[par], p.ovf_cnt[par], p.cnt[par ^ 1u],
+                       p.ovf_cnt[par ^ 1u], p.region, p.ovf, p.ord, k_abs, (BigAdapt*)nullptr,
+                       (unsigned long long*)nullptr, (double*)nullptr,
+                       (unsigned long long*)nullptr);
   }
   if (fork && (hipEventRecord(side.join, st2) != hipSuccess ||
                hipStreamWaitEvent(st, side.join, 0) != hipSuccess))
     return hipErrorUnknown;
+  return hipGetLastError();
+}
+
+hipError_t launch_abig_init(const PlanDev& p, uint32_t k_abs, hipStream_t st) {
+  hipLaunchKernelGGL(k_abig_init, dim3((p.n_abig + 255) / 256), dim3(256), 0, st, p.desc, p.big,
+                     p.abig, p.n_abig, p.astate[0], p.apmax[0], p.apmax[1], k_abs);
+  return hipGetLastError();
+}
+
+hipError_t launch_abig_round(const PlanDev& p, uint32_t k_abs, uint32_t round, uint32_t cnt_par,
+                             hipStream_t st) {
+  const uint32_t q = round & 1u, par = cnt_par & 1u;
+  hipLaunchKernelGGL(k_big_keys, dim3(p.n_achunks), dim3(kBigKeyThreads), 0, st, p.desc, p.big,
+                     p.achunks, p.cnt[par], p.ovf_cnt[par], p.region, p.ovf, k_abs,
+                     (const BigAdapt*)p.astate[q]);
+  hipLaunchKernelGGL(k_big_bucket<true>, dim3(p.n_abuckets), dim3(kBigThreads), 0, st, p.desc,
+                     p.big, p.abuckets, p.cnt[par], p.ovf_cnt[par], p.cnt[par ^ 1u],
+                     p.ovf_cnt[par ^ 1u], p.region, p.ovf, p.ord, k_abs, p.astate[q], p.apmax[q],
+                     p.apre, p.apair);
+  hipLaunchKernelGGL(k_abig_pairs, dim3(p.n_apblocks), dim3(kAbigPairs), 0, st, p.desc, p.big,
+                     p.apblocks, (const BigAdapt*)p.astate[q], p.astate[q ^ 1u],
+                     (const unsigned long long*)p.apmax[q], p.apmax[q ^ 1u],
+                     (const double*)p.apre, (const unsigned long long*)p.apair, k_abs);
+  return hipGetLastError();
+}
+
+hipError_t launch_abig_active(const PlanDev& p, uint32_t round, uint32_t* count,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_abig_active, dim3(1), dim3(256), 0, st,
+                     (const BigAdapt*)p.astate[round & 1u], p.abig, p.n_abig, count);
   return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 """GPU tests of the C ABI contract: a simulation busy on one stream refuses
 steps enqueued on another (SDM_EAGAIN) and enqueues nothing; set-up calls
 synchronise their own stream only."""
+import os
+
 import numpy as np
 import pytest
 
@@ -89,39 +91,17 @@ def test_eagain_when_member_busy_on_another_stream(B):
 
 
 def test_init_does_not_wait_for_other_streams(B):
-    """sdm_init on one stream returns while a long spin still runs on another.
-    Every device buffer is made, and used once by an untimed sdm_init on the
-    same stream, before the spin: the first use of memory torch has just
-    allocated can wait for other queues inside the HIP runtime (observed
-    only on that first use; no call of sdm_init synchronises the device), and
-    that is not the steady state a server admitting requests runs in."""
-    import gc
-    import time
+    """sdm_init synchronises its own stream only: checked in a fresh process
+    (tests/gpu_init_nowait.py), where the stream under test and the busy one
+    cannot share a hardware queue."""
+    import subprocess
+    import sys
 
-    import torch
-
-    busy, side = torch.cuda.Stream(), torch.cuda.Stream()
-    st = I.random_cells(8, 100, rng_seed=5)
-    cfg = B.make_config(st.n_slots, st.n_cells, st.n_attr, st.dt, st.dv, st.kernel,
-                        st.adaptive, st.b, st.seed)
-    xi = torch.from_numpy(st.xi).cuda()
-    v = torch.from_numpy(st.v).cuda()
-    off = torch.from_numpy(st.cell_off).cuda()
-    ws = B.workspace_tensor(B.sdm_workspace_bytes(cfg, st.cell_off))
-    B.sdm_free(B.sdm_init(cfg, xi, v, None, off, ws, side))
-    gc.collect()
-    torch.cuda.synchronize()
-    for rep in range(3):
-        _spin(busy, 400_000_000)
-        ev = torch.cuda.Event()
-        ev.record(busy)
-        t0 = time.perf_counter()
-        h = B.sdm_init(cfg, xi, v, None, off, ws, side)
-        dt_init = time.perf_counter() - t0
-        still_busy = not ev.query()
-        busy.synchronize()
-        dt_all = time.perf_counter() - t0
-        say(f"sdm_init {dt_init * 1e3:.2f} ms while the spin ran {dt_all * 1e3:.2f} ms; "
-            f"spin still running at return: {still_busy}")
-        assert still_busy, "sdm_init waited for work on another stream"
-        B.sdm_free(h)
+    say("init-does-not-wait check in a fresh process")
+    here = os.path.dirname(os.path.abspath(__file__))
+    r = subprocess.run([sys.executable, os.path.join(here, "gpu_init_nowait.py")],
+                       capture_output=True, text=True, timeout=180)
+    say(r.stdout.strip())
+    if r.returncode != 0:
+        say(r.stderr[-2000:])
+    assert r.returncode == 0, "sdm_init waited for work on another stream"

@@ -336,6 +336,85 @@ def test_adaptive_geometric_drizzle(B, orc):
     g.close()
 
 
+@pytest.mark.parametrize("case", ["box", "cells-big-path", "cells-overflow"])
+def test_adaptive_big_cells_bit_exact(B, orc, case):
+    """Adaptive substepping on the big-cell path (cells above the mid-size
+    limit, or every cell above 512 slots with mid_max_slots = 0): the Golovin
+    kernel with b raised so that cells take several substeps; state and the
+    last substep's pairs and gammas equal the oracle's at every step."""
+    if case == "box":
+        st = I.golovin_box(2 ** 15, seed=7)
+        st.b *= 3000.0
+        tuning = None
+    else:
+        st = I.random_cells(16, 3000, n_attr=2, rng_seed=35, p_boost=1e3)
+        tuning = dict(mid_max_slots=0)
+        if case == "cells-overflow":
+            tuning.update(big_bucket_target=64, big_bucket_cap=40)
+    st.adaptive = True
+    say(f"adaptive big cells: {case}")
+    g = GpuRun(B, st, sink=True, tuning=tuning)
+    o = st.copy()
+    cfg = ocfg(orc, o)
+    subs = 0
+    for s in range(4):
+        g.step(1)
+        out = orc.step(cfg, o.xi, o.v, o.attrs, o.cell_off, s, want_log=True, want_substeps=True)
+        subs = max(subs, int(out["substeps"].max()))
+        xi, v, at = g.state()
+        assert np.array_equal(xi, o.xi), s
+        assert np.array_equal(v, o.v) and np.array_equal(at, o.attrs), s
+        assert np.array_equal(g.log(), out["log"]), s
+    stats = B.sdm_stats(g.sim.handle)
+    say(f"  most substeps in a step {subs}; stats {stats}")
+    assert subs > 1 and stats["cell_substeps"] > stats["cell_steps"]
+    g.close()
+
+
+def test_adaptive_big_geometric_teacher_forced(B, orc):
+    """The 2^17 geometric box in adaptive mode at dt = 30 s (so that it
+    substeps): teacher-forced per step, differing steps within 1e-6 of the
+    pair-substeps (last-bit cube-root differences)."""
+    st = I.geometric_box(2 ** 17)
+    st.adaptive = True
+    st.dt = 30.0
+    g = GpuRun(B, st, sink=True)
+    cfg = ocfg(orc, st)
+    bad = pair_substeps = 0
+    for s in range(3):
+        xi0, v0, a0 = g.state()
+        o_xi, o_v, o_a = xi0.copy(), v0.copy(), np.ascontiguousarray(a0.copy())
+        live = int((o_xi > 0).sum())
+        g.step(1)
+        out = orc.step(cfg, o_xi, o_v, o_a, st.cell_off, s, want_substeps=True)
+        xi, v, _ = g.state()
+        pair_substeps += int(out["substeps"][0]) * (live // 2)
+        if not (np.array_equal(xi, o_xi) and rel_close(v, o_v, 1e-12)):
+            bad += 1
+        say(f"  step {s}: substeps {int(out['substeps'][0])}")
+    allowed = int(1e-6 * pair_substeps)
+    say(f"  differing steps {bad} of {pair_substeps} pair-substeps (allowed {allowed})")
+    assert bad <= allowed
+    assert B.sdm_stats(g.sim.handle)["cell_substeps"] > 3
+    g.close()
+
+
+def test_adaptive_big_substep_cap(B, orc):
+    st = I.golovin_box(2 ** 15, seed=2)
+    st.b *= 3000.0
+    st.adaptive = True
+    g = GpuRun(B, st, sink=False, max_substeps=1)
+    o = st.copy()
+    cfg = ocfg(orc, o, max_substeps=1)
+    g.step(1)
+    out = orc.step(cfg, o.xi, o.v, o.attrs, o.cell_off, 0)
+    assert out["status"] & orc.ST_SUBSTEP_CAP
+    assert B.sdm_status_word(g.sim.handle) & B.SDM_FLAG_SUBSTEP_CAP
+    xi, v, _ = g.state()
+    assert np.array_equal(xi, o.xi) and np.array_equal(v, o.v)
+    g.close()
+
+
 def test_substep_cap_flag(B, orc):
     st = I.grid(4, 4, 64, kernel=I.GEOMETRIC, drizzle=True, adaptive=True)
     g = GpuRun(B, st, sink=False, max_substeps=1)
@@ -516,10 +595,6 @@ def test_invalid_inputs(B):
     bad.cell_off[2] = bad.cell_off[3] + 1
     with pytest.raises(B.SdmError):
         B.Sim(bad)
-    big = I.golovin_box(20000)  # adaptive mode takes cells of up to 16384 slots
-    big.adaptive = True
-    with pytest.raises(B.SdmError):
-        B.Sim(big)
     cfg = B.make_config(st.n_slots, st.n_cells)
     small = torch.empty(256, dtype=torch.uint8, device="cuda")
     xi = torch.from_numpy(st.xi).cuda()
