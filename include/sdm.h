@@ -37,7 +37,8 @@
  *     m^3), attrs[n_attr][n_slots] (float64, extra extensive attributes summed
  *     on coalescence like volume), cell_off[n_cells + 1] (int64, slots of cell
  *     c are [cell_off[c], cell_off[c+1]), cell_off[0] = 0, cell_off[n_cells] =
- *     n_slots).  An SD with xi = 0 is dead and keeps its slot.
+ *     n_slots, at most 8 388 608 slots per cell: a layout with a larger cell
+ *     is invalid).  An SD with xi = 0 is dead and keeps its slot.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).
  *
  * Errors.  Every call returns an sdm_status; nothing aborts and no exception
@@ -125,9 +126,9 @@ typedef struct {
   int32_t mid_max_slots;     /* cells of 513..mid_max_slots slots (<= 16384) get one workgroup
                                 each (mid-size kernel); larger ones take the big-cell path
                                 (two launches per step); 0 sends every cell above 512 there */
-  int32_t big_bucket_cap;    /* big-cell path: entries stored per bucket before the rest go to
-                                an overflow list (still exact, slower); 0 = twice
-                                big_bucket_target, else 1..2 x big_bucket_target */
+  int32_t big_bucket_cap;    /* big-cell path: longest bucket one workgroup orders in LDS;
+                                longer ones are ranked in global memory (still exact,
+                                slower, SDM_FLAG_BUCKET_OVERFLOW); 0 = 1024, else 1..1024 */
 } sdm_tuning;
 
 /*
@@ -164,7 +165,8 @@ sdm_status sdm_coalescence_step(sdm_sim* s, int32_t n_steps, void* stream);
  * NULL): m0[C] = sum xi (int64, exact); m12[C][2] = (sum xi v, sum xi v^2);
  * attr_sums[C][A] = sum xi a_q; spectrum[C][n_bins] = sum xi v over SDs with
  * vol_edges[k] <= v < vol_edges[k+1] (vol_edges: device, n_bins + 1 increasing
- * volumes [m^3]; SDs outside are dropped).  dm/dlnr of bin k is
+ * volumes [m^3], 1 <= n_bins <= 1024; SDs outside are dropped).  One pass over
+ * each cell's slots.  dm/dlnr of bin k is
  * rho_w spectrum / dV / ln(r_{k+1} / r_k).  Sums use a fixed reduction order,
  * so a cell's moments do not depend on the rest of the state.
  */

@@ -58,15 +58,24 @@ bool tuning_ok(const sdm_tuning& t) {
   return (w == 1 || w == 2 || w == 4 || w == 8) && t.big_bucket_target >= sdm::kMinBucketTarget &&
          t.big_bucket_target <= 1024 && (t.wave_class_mask & ~sdm::kClassAll) == 0 &&
          t.mid_max_slots >= 0 && t.mid_max_slots <= sdm::kMidCapMax && t.big_bucket_cap >= 0 &&
-         t.big_bucket_cap <= 2 * t.big_bucket_target;
+         t.big_bucket_cap <= 1024;
 }
 
-// entries of a big cell's bucket region (the tuning's cap, else twice the
-// expected bucket size)
-int big_cap(const sdm_tuning& t) {
-  return t.big_bucket_cap > 0 ? t.big_bucket_cap : 2 * t.big_bucket_target;
+// The chunking and bucketing of a big cell of n slots: at most kBigMaxChunks
+// key blocks of a multiple of kBigChunkUnit slots, at most kBigMaxBuckets
+// buckets.
+struct BigShape {
+  int32_t nb, n_chunks, chunk_slots;
+};
+BigShape big_shape(int64_t n, const sdm_tuning& t) {
+  BigShape b;
+  b.nb = (int32_t)std::min<int64_t>(
+      sdm::kBigMaxBuckets, std::max<int64_t>(1, (n + t.big_bucket_target - 1) / t.big_bucket_target));
+  const int64_t unit = (int64_t)sdm::kBigChunkUnit * sdm::kBigMaxChunks;
+  b.chunk_slots = (int32_t)(sdm::kBigChunkUnit * std::max<int64_t>(1, (n + unit - 1) / unit));
+  b.n_chunks = (int32_t)std::max<int64_t>(1, (n + b.chunk_slots - 1) / b.chunk_slots);
+  return b;
 }
-constexpr int64_t kBigRegionSlack = 2 * 1024;  // region entries beyond 2 n per big cell, at most
 
 }  // namespace
 
@@ -186,9 +195,8 @@ struct Tables {
   std::vector<BigChunk> achunks;
   std::vector<BigBucket> abuckets;
   std::vector<BigPairBlock> apblocks;
-  int64_t tmp_total = 0;     // slots of big cells (overflow and order entries)
-  int64_t region_total = 0;  // bucket-region entries
-  int64_t bucket_total = 0;
+  int64_t tmp_total = 0;  // slots of big cells (entries, order)
+  int64_t off_total = 0;  // words of the chunks' bucket offsets
   int64_t n_wave_total() const {
     int64_t n = 0;
     for (auto& w : wave) n += (int64_t)w.size();
@@ -228,20 +236,22 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
       t.sim = i;
       t.cell = c;
       t.n_slots = (int32_t)n;
-      t.nb = (int32_t)std::max<int64_t>(1, (n + tu.big_bucket_target - 1) / tu.big_bucket_target);
-      t.cap = big_cap(tu);
-      t.region_base = T.region_total;
-      T.region_total += (int64_t)t.nb * t.cap;
+      const BigShape bs = big_shape(n, tu);
+      t.nb = bs.nb;
+      t.n_chunks = bs.n_chunks;
+      t.chunk_slots = bs.chunk_slots;
+      t.sort_cap = tu.big_bucket_cap > 0 ? tu.big_bucket_cap : 1024;
+      t.pad = 0;
       t.tmp_base = T.tmp_total;
       T.tmp_total += n;
-      t.bucket_base = (int32_t)T.bucket_total;
-      T.bucket_total += t.nb;
+      t.off_base = T.off_total;
+      T.off_total += (int64_t)t.n_chunks * (t.nb + 1);
       const int ti = (int)T.big.size();
       T.big.push_back(t);
       const bool ad = ms[i]->cfg.adaptive != 0;
-      for (int64_t f = 0; f < n; f += sdm::kChunk)
-        (ad ? T.achunks : T.chunks).push_back({ti, (int32_t)f});
-      for (int b = 0; b < t.nb; ++b) (ad ? T.abuckets : T.buckets).push_back({ti, b});
+      for (int32_t f = 0; f < t.n_chunks; ++f)
+        (ad ? T.achunks : T.chunks).push_back({ti, f, t.sim, 0});
+      for (int32_t b = 0; b < t.nb; ++b) (ad ? T.abuckets : T.buckets).push_back({ti, b, t.sim, 0});
       if (ad) {
         T.abig.push_back(ti);
         for (int64_t m = 0; m < n / 2; m += sdm::kAbigPairs)
@@ -275,8 +285,8 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
 
 struct Layout {
   size_t desc, wave[sdm::kNumClasses], wave_alt[sdm::kNumClasses], order_flag[sdm::kNumClasses],
-      order_cnt[sdm::kNumClasses], mid[sdm::kNumMid], big, chunks, buckets, cnt[2], ovf_cnt[2],
-      region, ovf, ord, abig, achunks, abuckets, apblocks, astate[2], apmax[2], apre, apair,
+      order_cnt[sdm::kNumClasses], mid[sdm::kNumMid], big, chunks, buckets, ekey, exi, ev, offs,
+      skey, ord, abig, achunks, abuckets, apblocks, astate[2], apmax[2], apre, apair,
       aactive, total;
 };
 
@@ -301,13 +311,13 @@ static Layout layout_of(int n_members, const Tables& T) {
   L.big = take(sizeof(BigTask) * std::max<size_t>(T.big.size(), 1));
   L.chunks = take(sizeof(BigChunk) * std::max<size_t>(T.chunks.size(), 1));
   L.buckets = take(sizeof(BigBucket) * std::max<size_t>(T.buckets.size(), 1));
-  for (int k = 0; k < 2; ++k) {
-    L.cnt[k] = take(sizeof(uint32_t) * std::max<int64_t>(T.bucket_total, 1));
-    L.ovf_cnt[k] = take(sizeof(uint32_t) * std::max<size_t>(T.big.size(), 1));
-  }
-  L.region = take(sizeof(unsigned long long) * std::max<int64_t>(T.region_total, 1));
-  L.ovf = take(sizeof(unsigned long long) * std::max<int64_t>(T.tmp_total, 1));
-  L.ord = take(sizeof(uint32_t) * std::max<int64_t>(T.tmp_total, 1));
+  const size_t nt = (size_t)std::max<int64_t>(T.tmp_total, 1);
+  L.ekey = take(sizeof(unsigned long long) * nt);
+  L.exi = take(sizeof(long long) * nt);
+  L.ev = take(sizeof(double) * nt);
+  L.offs = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(T.off_total, 1));
+  L.skey = take(sizeof(unsigned long long) * nt);
+  L.ord = take(sizeof(uint32_t) * nt);
   const bool ad = !T.abig.empty();
   L.abig = take(sizeof(int) * std::max<size_t>(T.abig.size(), 1));
   L.achunks = take(sizeof(BigChunk) * std::max<size_t>(T.achunks.size(), 1));
@@ -339,12 +349,9 @@ static size_t plan_bytes_worst(const std::vector<sdm_sim*>& ms) {
       const int64_t n = s->off[c + 1] - s->off[c];
       n_mid += (n > sdm::kWaveCapMax && n <= sdm::kMidCapMax) ? 1 : 0;
     }
-  // bucket regions: nb x cap <= (n / target + 1) 2 target <= 2 n + 2 target
-  // entries for any target; the smallest target gives the most counters
-  const size_t region_extra =
-      sizeof(unsigned long long) * (size_t)kBigRegionSlack * T.big.size();
+  // the smallest target gives the most buckets, so the most offsets
   return layout_of((int)ms.size(), T).total + align_up(sizeof(sdm::CellTask) * n_mid) +
-         align_up(region_extra) + (4 * sdm::kNumClasses + sdm::kNumMid) * kAlign;
+         (4 * sdm::kNumClasses + sdm::kNumMid) * kAlign;
 }
 
 struct Plan {
@@ -357,8 +364,6 @@ struct Plan {
   std::vector<SimDesc> desc;  // host copy of the device descriptors
   uint32_t counter = 0;       // launch step of the next step
   uint32_t flip = 0;          // launches since the tables were built
-  uint32_t big_steps = 0;     // big-cell steps launched since the tables were built
-  uint32_t abig_rounds = 0;   // adaptive big-cell substep rounds launched since then
   sdm::SideStream side;       // created at the first step
   std::shared_ptr<Busy> busy;  // event recorded after each step call, created at the first
   Plan() = default;
@@ -463,12 +468,11 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   d.n_chunks = (int)p->T.chunks.size();
   d.buckets = reinterpret_cast<const BigBucket*>(w + L.buckets);
   d.n_buckets = (int)p->T.buckets.size();
-  for (int k = 0; k < 2; ++k) {
-    d.cnt[k] = reinterpret_cast<uint32_t*>(w + L.cnt[k]);
-    d.ovf_cnt[k] = reinterpret_cast<uint32_t*>(w + L.ovf_cnt[k]);
-  }
-  d.region = reinterpret_cast<unsigned long long*>(w + L.region);
-  d.ovf = reinterpret_cast<unsigned long long*>(w + L.ovf);
+  d.ekey = reinterpret_cast<unsigned long long*>(w + L.ekey);
+  d.exi = reinterpret_cast<long long*>(w + L.exi);
+  d.ev = reinterpret_cast<double*>(w + L.ev);
+  d.offs = reinterpret_cast<uint32_t*>(w + L.offs);
+  d.skey = reinterpret_cast<unsigned long long*>(w + L.skey);
   d.ord = reinterpret_cast<uint32_t*>(w + L.ord);
   d.abig = reinterpret_cast<const int*>(w + L.abig);
   d.n_abig = (int)p->T.abig.size();
@@ -485,8 +489,6 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   d.apre = reinterpret_cast<double*>(w + L.apre);
   d.apair = reinterpret_cast<unsigned long long*>(w + L.apair);
   d.aactive = reinterpret_cast<uint32_t*>(w + L.aactive);
-  p->big_steps = 0;
-  p->abig_rounds = 0;
 
   // the old tables may still be read by steps enqueued on `st`
   HIP_TRY(hipStreamSynchronize(st));
@@ -510,10 +512,6 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   HIP_TRY(upload(const_cast<BigChunk*>(d.achunks), p->T.achunks, st));
   HIP_TRY(upload(const_cast<BigBucket*>(d.abuckets), p->T.abuckets, st));
   HIP_TRY(upload(const_cast<BigPairBlock*>(d.apblocks), p->T.apblocks, st));
-  for (int k = 0; k < 2 && !p->T.big.empty(); ++k) {  // both sets of counters start at zero
-    HIP_TRY(hipMemsetAsync(d.cnt[k], 0, sizeof(uint32_t) * p->T.bucket_total, st));
-    HIP_TRY(hipMemsetAsync(d.ovf_cnt[k], 0, sizeof(uint32_t) * p->T.big.size(), st));
-  }
   if (sync_end) HIP_TRY(hipStreamSynchronize(st));
   return SDM_OK;
 }
@@ -548,7 +546,7 @@ static sdm_status abig_step(Plan* p, uint32_t k_abs, hipStream_t st) {
   // a capped substep ends a cell's step: umax + 1 rounds always suffice
   for (uint32_t r = 0; r <= umax;) {
     for (int i = 0; i < sdm::kAbigRoundsPerCheck && r <= umax; ++i, ++r)
-      if (sdm::launch_abig_round(p->dev, k_abs, r, p->abig_rounds++, st) != hipSuccess)
+      if (sdm::launch_abig_round(p->dev, k_abs, r, st) != hipSuccess)
         return SDM_EDEVICE;
     uint32_t active = 0;
     if (sdm::launch_abig_active(p->dev, r, p->dev.aactive, st) != hipSuccess ||
@@ -595,10 +593,9 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
   }
   for (int64_t k = 0; k < active;) {  // up to kFuseMax steps per launch
     const int f = (int)std::min<int64_t>(sdm::kFuseMax, active - k);
-    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->flip++, p->big_steps, f,
+    if (sdm::launch_step(p->dev, p->counter + (uint32_t)k, p->flip++, f,
                          p->tuning.waves_per_cell, st, p->side) != hipSuccess)
       return SDM_EDEVICE;
-    p->big_steps += (uint32_t)f;
     for (int t = 0; t < f && p->dev.n_abig > 0; ++t) {  // adaptive big cells: substep rounds
       const sdm_status r2 = abig_step(p, p->counter + (uint32_t)(k + t), st);
       if (r2 != SDM_OK) return r2;
@@ -656,7 +653,7 @@ static bool cfg_ok(const sdm_config* c) {
 static bool offsets_ok(const sdm_config* c, const int64_t* off) {
   if (off[0] != 0 || off[c->n_cells] != c->n_slots) return false;
   for (int i = 0; i < c->n_cells; ++i)
-    if (off[i + 1] < off[i]) return false;
+    if (off[i + 1] < off[i] || off[i + 1] - off[i] > sdm::kBigMaxSlots) return false;
   return true;
 }
 
@@ -683,21 +680,23 @@ static size_t plan_bytes_bound(const sdm_config* c) {
     take(sizeof(uint32_t) * sdm::kOrderGroups * (size_t)(C / sdm::kOrderBlock + 1));
   }
   take(sizeof(BigTask) * (size_t)std::max<int64_t>(nbig, 1));
-  take(sizeof(BigChunk) * (size_t)(ns / sdm::kChunk + nbig + 1));
+  const int64_t nchk = ns / sdm::kBigChunkUnit + nbig + 1;
+  take(sizeof(BigChunk) * (size_t)nchk);
   const int64_t nbk = ns / sdm::kMinBucketTarget + nbig + 1;
   take(sizeof(BigBucket) * (size_t)nbk);
-  for (int k = 0; k < 2; ++k) {
-    take(sizeof(uint32_t) * (size_t)nbk);
-    take(sizeof(uint32_t) * (size_t)std::max<int64_t>(nbig, 1));
-  }
-  take(sizeof(unsigned long long) * (size_t)(2 * ns + kBigRegionSlack * nbig + 1));
-  take(sizeof(unsigned long long) * (size_t)std::max<int64_t>(ns, 1));
-  take(sizeof(uint32_t) * (size_t)std::max<int64_t>(ns, 1));
+  const size_t nt = (size_t)std::max<int64_t>(ns, 1);
+  take(sizeof(unsigned long long) * nt);  // entries: keys, multiplicities, volumes
+  take(sizeof(long long) * nt);
+  take(sizeof(double) * nt);
+  // offsets: n_chunks (nb + 1) <= 8 n + 1024 words for a cell of n slots
+  take(sizeof(uint32_t) * (size_t)(8 * ns + 1024 * nbig + 1));
+  take(sizeof(unsigned long long) * nt);  // slow-path keys and order
+  take(sizeof(uint32_t) * nt);
   // adaptive big cells: task list, chunks and buckets (counted above once),
   // pair blocks, per-cell state and largest p, per-pair pre-products and slots
   const bool ad = c->adaptive != 0;
   take(sizeof(int) * (size_t)std::max<int64_t>(nbig, 1));
-  take(sizeof(BigChunk) * (size_t)(ad ? ns / sdm::kChunk + nbig + 1 : 1));
+  take(sizeof(BigChunk) * (size_t)(ad ? nchk : 1));
   take(sizeof(BigBucket) * (size_t)(ad ? nbk : 1));
   take(sizeof(BigPairBlock) * (size_t)(ad ? ns / (2 * sdm::kAbigPairs) + nbig + 1 : 1));
   for (int k = 0; k < 2; ++k) {
@@ -821,9 +820,11 @@ sdm_status sdm_coalescence_step(sdm_sim* s, int32_t n_steps, void* stream) {
 sdm_status sdm_moments(sdm_sim* s, int64_t* m0, double* m12, double* attr_sums,
                        const double* vol_edges, int32_t n_bins, double* spectrum, void* stream) {
   if (!s || n_bins < 0) return SDM_EINVAL;
-  if (spectrum && (!vol_edges || n_bins < 1)) return SDM_EINVAL;
+  if (spectrum && (!vol_edges || n_bins < 1 || n_bins > sdm::kMomentsMaxBins)) return SDM_EINVAL;
   const SimDesc d = make_desc(s, 0);
-  if (sdm::launch_moments(d, s->cfg.n_cells, m0, m12, attr_sums, vol_edges,
+  // one wave per cell when cells hold 256 slots or fewer on average
+  const int waves = s->cfg.n_slots <= 256 * (int64_t)s->cfg.n_cells ? 1 : 4;
+  if (sdm::launch_moments(d, s->cfg.n_cells, waves, m0, m12, attr_sums, vol_edges,
                           spectrum ? n_bins : 0, spectrum,
                           reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return SDM_EDEVICE;

@@ -13,13 +13,17 @@ constexpr int kNumClasses = 5;    // workgroup-per-cell capacities 64, 128, 256,
 constexpr int kWaveCapMax = 512;  // cells above this go to the mid-size or big-cell path
 constexpr int kNumMid = 4;        // mid-size capacities 2048, 4096, 8192, 16384 slots
 constexpr int kMidCapMax = 16384;
-constexpr int kChunk = 4096;      // slots per block of the big-cell key pass
+constexpr int kBigChunkUnit = 1024;   // slots per Philox round of a big-cell key block
+constexpr int kBigMaxChunks = 256;    // key blocks per big cell, at most
+constexpr int kBigMaxBuckets = 8192;  // buckets per big cell, at most (one LDS histogram)
+constexpr int64_t kBigMaxSlots = 8388608;  // slots per cell, at most (kBigMaxBuckets x 1024)
 constexpr int kAbigPairs = 256;   // pairs per block of the adaptive big-cell pair pass
 constexpr int kAbigRoundsPerCheck = 4;  // adaptive big-cell substep rounds between host checks
 constexpr int kMinBucketTarget = 32;
 constexpr int kOrderBlock = 1024;  // tasks per block of the dispatch-order partition
 constexpr int kOrderGroups = 4;    // dispatch-order groups by substeps taken
 constexpr int kFuseMax = 8;        // steps of a multi-step call fused in one launch
+constexpr int kMomentsMaxBins = 1024;  // spectrum bins of sdm_moments, at most
 
 constexpr uint32_t kFlagSubstepCap = 1u;
 constexpr uint32_t kFlagGammaCap = 2u;
@@ -66,30 +70,38 @@ struct CellTask {
   int32_t pad;
 };
 
-// A cell above the mid-size limit: its live slots are spread over nb
-// buckets (key ranges) of cap entries each, then each bucket is ordered and
-// paired by one workgroup.
+// A cell above the mid-size limit.  Its slots are split into n_chunks
+// chunks of chunk_slots; the key pass writes each chunk's live entries into
+// the chunk's own segment of the entry arrays, grouped by bucket (nb key
+// ranges), with nb + 1 offsets per chunk; each bucket is then gathered,
+// ordered and paired by one workgroup.
 struct BigTask {
   int64_t* xi;  // first slot of the cell
   double* v;
-  int64_t region_base;  // first entry of the cell's nb x cap bucket regions
-  int64_t tmp_base;     // first entry of the cell in the overflow and order buffers
+  int64_t tmp_base;  // first entry of the cell in the entry and order arrays (n_slots)
+  int64_t off_base;  // first word of the cell's offsets (n_chunks x (nb + 1))
   int32_t sim;
   int32_t cell;
-  int32_t bucket_base;  // first of the cell's nb bucket counters
-  int32_t nb;
-  int32_t cap;
+  int32_t nb;           // buckets, 1..kBigMaxBuckets
+  int32_t n_chunks;     // 1..kBigMaxChunks
+  int32_t chunk_slots;  // a multiple of kBigChunkUnit
+  int32_t sort_cap;     // longest bucket ordered in LDS (longer: ranked in global memory)
   int32_t n_slots;
+  int32_t pad;
 };
 
-struct BigChunk {  // kChunk consecutive slots of one big cell
+struct BigChunk {  // chunk_slots consecutive slots of one big cell
   int32_t task;
-  int32_t first;
+  int32_t index;  // chunk of the cell: slots [index chunk_slots, (index + 1) chunk_slots)
+  int32_t sim;    // the task's simulation (read beside the task)
+  int32_t pad;
 };
 
 struct BigBucket {  // one bucket of one big cell
   int32_t task;
   int32_t bucket;
+  int32_t sim;  // the task's simulation (read beside the task)
+  int32_t pad;
 };
 
 struct BigPairBlock {  // consecutive pairs of one adaptive big cell
@@ -129,13 +141,15 @@ struct PlanDev {
   int n_chunks;
   const BigBucket* buckets;
   int n_buckets;
-  // two sets of bucket and overflow counters: a step fills one and clears
-  // the other for the next step
-  uint32_t* cnt[2];
-  uint32_t* ovf_cnt[2];
-  unsigned long long* region;  // bucket regions
-  unsigned long long* ovf;     // overflow entries (a full bucket's extra entries)
-  uint32_t* ord;               // order of a bucket ranked in global memory
+  // entries of every big cell, by chunk, grouped by bucket: (key << 32 |
+  // slot), multiplicity and volume; the chunks' bucket offsets; a bucket
+  // ranked in global memory (longer than the LDS stage): its keys and order
+  unsigned long long* ekey;
+  long long* exi;
+  double* ev;
+  uint32_t* offs;
+  unsigned long long* skey;
+  uint32_t* ord;
   // adaptive big cells: their tasks, key chunks, buckets and pair blocks;
   // per-cell state and largest p (two copies alternating by round); per
   // pair pre-products and slots
@@ -165,18 +179,18 @@ struct SideStream {
 // workgroup-per-cell classes in one launch each (several steps fused), the
 // mid-size and big cells one step per launch.  flip: launches made on this
 // plan since its tables were built (selects which of the two adaptive task
-// lists is read); big_step: big-cell steps launched since then (selects the
-// set of bucket counters).
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, uint32_t big_step,
-                       int nsteps, int waves_per_cell, hipStream_t st, const SideStream& side);
+// lists is read).
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
+                       int waves_per_cell, hipStream_t st, const SideStream& side);
 // Adaptive big cells: the start of an outer step (every cell's state
 // reset), one substep round (keys, order and pre-products, pairs), and the
 // count of cells still stepping after a round, into a device word.
 hipError_t launch_abig_init(const PlanDev& p, uint32_t k_abs, hipStream_t st);
-hipError_t launch_abig_round(const PlanDev& p, uint32_t k_abs, uint32_t round, uint32_t cnt_par,
-                             hipStream_t st);
+hipError_t launch_abig_round(const PlanDev& p, uint32_t k_abs, uint32_t round, hipStream_t st);
 hipError_t launch_abig_active(const PlanDev& p, uint32_t round, uint32_t* count, hipStream_t st);
-hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
+// Per-cell moments, one workgroup of `waves` (1 or 4) wavefronts per cell;
+// n_bins <= kMomentsMaxBins.
+hipError_t launch_moments(const SimDesc& d, int n_cells, int waves, int64_t* m0, double* m12,
                           double* attr_sums, const double* edges, int n_bins, double* spectrum,
                           hipStream_t st);
 hipError_t launch_validate(const int64_t* xi, const double* v, int64_t n, uint32_t* status,

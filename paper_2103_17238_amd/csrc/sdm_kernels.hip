@@ -1105,50 +1105,70 @@ __global__ void __launch_bounds__(64 * W) k_cells_mid(const SimDesc* __restrict_
 // ---------------------------------------------------------------------------
 // Big cells (above the mid-size limit): two launches per step.
 //
-// k_big_keys: every live slot's key goes to bucket floor(key nb / 2^32) of
-// its cell (nb buckets, a monotone map of the key, so buckets are key
-// ranges in order); the entry (key << 32 | slot) is stored at the bucket's
-// next free place in a fixed-capacity region, or, when the bucket is full,
-// appended to the cell's overflow list.
-// k_big_bucket: one workgroup per bucket.  The bucket's first position in
-// the cell's permutation is the sum of the counts of the buckets before it;
-// its entries are ordered in LDS (a sub-bucket scatter on the key's position
-// inside the bucket range, then an exact rank inside each sub-bucket), and
-// the workgroup takes every pair whose first member sits at an even
-// position of its range: the partner is the next entry, or, for the last
-// entry, the smallest entry of the next non-empty bucket.  A bucket longer
-// than its region or than the LDS stage is ranked in global memory instead
-// (exact, slow, flagged).  The counters of one step are cleared by the
-// other step's bucket kernel (two sets, alternating).
+// k_big_keys: one block per chunk of a cell's slots.  Every live slot's key
+// goes to bucket floor(key nb / 2^32) of its cell (nb buckets, a monotone
+// map of the key, so buckets are key ranges in order).  The block counts its
+// chunk per bucket in LDS, turns the counts into the chunk's own bucket
+// offsets (stored: nb + 1 words, the last one the chunk's live count) and
+// writes each entry (key << 32 | slot), with the slot's multiplicity and
+// volume, at its place in the chunk's segment of the entry arrays.  No
+// global atomics and no capacity: a segment holds exactly its chunk's live
+// slots.
+// k_big_bucket: one workgroup per bucket.  From the offsets of every chunk it
+// takes the bucket's first position in the cell's permutation (the entries
+// of all chunks in the buckets before it), its length and the cell's live
+// count; it gathers the bucket's entries from the chunk segments, orders
+// them in LDS (a sub-bucket scatter on the key's position inside the bucket
+// range, then an exact rank inside each sub-bucket), and takes every pair
+// whose first member sits at an even position of the permutation: the
+// partner is the next entry, or, for the last one, the smallest entry of
+// the next non-empty bucket, gathered in the same pass.  Multiplicities and
+// volumes travel with the entries, so the pairs need no state reads (only
+// attributes are read back).  A bucket longer than the LDS stage is ranked in
+// global memory instead (exact, slow, flagged).
 // ---------------------------------------------------------------------------
 constexpr int kBigKeyThreads = 256;
-constexpr int kBigKeyGroups = kChunk / (4 * kBigKeyThreads);  // Philox groups per thread
-constexpr int kBigKeyLdsBuckets = 8192;  // bucket histogram of one block in LDS
-static_assert(kBigKeyGroups * 4 * kBigKeyThreads == kChunk, "a block covers one chunk");
 constexpr int kBigThreads = 256;
 constexpr int kBigSortCap = 1024;  // entries one workgroup orders in LDS
+constexpr int kBigPer = kBigSortCap / kBigThreads;
+static_assert(kBigChunkUnit == 4 * kBigKeyThreads, "a Philox round covers one chunk unit");
+static_assert(kBigMaxChunks == kBigThreads, "one chunk per thread of a bucket workgroup");
 
 __device__ __forceinline__ uint32_t key_bucket(uint32_t key, uint32_t nb) {
   return (uint32_t)(((unsigned long long)key * nb) >> 32);
 }
 
-// Each block takes kChunk slots (kBigKeyGroups Philox groups of 4 per
-// thread).  Its bucket counts are made in LDS, then one global atomic per
-// (block, bucket) reserves the block's places in the bucket: a bucket
-// counter sees as many atomics as the cell has blocks, not as many as it
-// has entries (counters of one cell are hit from every XCD).  Cells with
-// more buckets than the LDS histogram holds take one global atomic per
-// entry.
+// exclusive scan of h[0, n) in place (n <= kBigMaxBuckets), h[n] = total;
+// each thread a contiguous run, fixed order
+__device__ void chunk_scan(uint32_t* h, int n, int* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int R = (n + kBigKeyThreads - 1) / kBigKeyThreads;
+  const int a = min(tid * R, n), e = min(a + R, n);
+  int local = 0;
+  for (int i = a; i < e; ++i) local += (int)h[i];
+  int run = wave_excl_scan(local, lane);
+  if (lane == 63) red[wv] = run + local;
+  __syncthreads();
+  for (int k = 0; k < wv; ++k) run += red[k];
+  if (tid == kBigKeyThreads - 1) h[n] = (uint32_t)(run + local);
+  for (int i = a; i < e; ++i) {
+    const uint32_t c = h[i];
+    h[i] = (uint32_t)run;
+    run += (int)c;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kBigKeyThreads) k_big_keys(
     const SimDesc* __restrict__ descs, const BigTask* __restrict__ big,
-    const BigChunk* __restrict__ chunks, uint32_t* __restrict__ cnt,
-    uint32_t* __restrict__ ovf_cnt, unsigned long long* __restrict__ region,
-    unsigned long long* __restrict__ ovf, uint32_t k_abs,
-    const BigAdapt* __restrict__ astate) {
-  __shared__ uint32_t hist[kBigKeyLdsBuckets];
+    const BigChunk* __restrict__ chunks, uint32_t* __restrict__ offs,
+    unsigned long long* __restrict__ ekey, long long* __restrict__ exi,
+    double* __restrict__ ev, uint32_t k_abs, const BigAdapt* __restrict__ astate) {
+  __shared__ uint32_t hist[kBigMaxBuckets + 1];
+  __shared__ int red[kBigKeyThreads / 64];
   const BigChunk ch = chunks[blockIdx.x];
   const BigTask tk = big[ch.task];
-  const SimDesc* dp = descs + tk.sim;
+  const SimDesc* dp = descs + ch.sim;
   const uint32_t s = k_abs + dp->step_delta;
   if (s >= dp->step_limit) return;
   uint32_t u = 0;  // substep (adaptive cells: this round's, from the cell's state)
@@ -1157,149 +1177,164 @@ __global__ void __launch_bounds__(kBigKeyThreads) k_big_keys(
     if (as.done) return;
     u = as.u;
   }
+  const int tid = threadIdx.x;
   const uint32_t nb = (uint32_t)tk.nb;
-  const bool local = nb <= (uint32_t)kBigKeyLdsBuckets;
-  if (local) {
-    for (uint32_t i = threadIdx.x; i < nb; i += kBigKeyThreads) hist[i] = 0;
-    __syncthreads();
-  }
-  uint32_t kk[kBigKeyGroups][4], bkt[kBigKeyGroups][4], pos[kBigKeyGroups][4];
+  const int first = ch.index * tk.chunk_slots;
+  const int last = min(first + tk.chunk_slots, tk.n_slots);
+  for (uint32_t i = tid; i <= nb; i += kBigKeyThreads) hist[i] = 0;
+  __syncthreads();
+  const int64_t seg = tk.tmp_base + first;  // this chunk's segment
+  uint32_t* o = offs + tk.off_base + (int64_t)ch.index * (nb + 1u);
+  if (tk.chunk_slots == kBigChunkUnit) {
+    // one Philox group of 4 slots per thread: places and values in registers
+    const int j0 = first + 4 * tid;
+    long long xv[4] = {0, 0, 0, 0};
+    double vv[4] = {0.0, 0.0, 0.0, 0.0};
+    uint32_t kk[4] = {0u, 0u, 0u, 0u}, bkt[4] = {0u, 0u, 0u, 0u};
+    uint32_t pos[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    if (j0 < last) {
 #pragma unroll
-  for (int r = 0; r < kBigKeyGroups; ++r) {
-    const int g = ch.first / 4 + r * kBigKeyThreads + (int)threadIdx.x;
-    const int j0 = 4 * g;
+      for (int e = 0; e < 4; ++e)
+        if (j0 + e < last) {
+          xv[e] = tk.xi[j0 + e];
+          vv[e] = tk.v[j0 + e];
+        }
+      const uint4 w = philox(make_uint4((uint32_t)(j0 >> 2), (uint32_t)tk.cell, s, 2u * u),
+                             dp->seed_lo, dp->seed_hi);
+      kk[0] = w.x;
+      kk[1] = w.y;
+      kk[2] = w.z;
+      kk[3] = w.w;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) pos[r][e] = 0xFFFFFFFFu;
-    if (j0 >= tk.n_slots || j0 >= ch.first + kChunk) continue;
-    long long xv[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) xv[e] = j0 + e < tk.n_slots ? tk.xi[j0 + e] : 0;
-    const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)tk.cell, s, 2u * u), dp->seed_lo,
-                           dp->seed_hi);
-    kk[r][0] = w.x;
-    kk[r][1] = w.y;
-    kk[r][2] = w.z;
-    kk[r][3] = w.w;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      bkt[r][e] = key_bucket(kk[r][e], nb);
-      if (xv[e] > 0)
-        pos[r][e] = local ? atomicAdd(&hist[bkt[r][e]], 1u)
-                          : atomicAdd(&cnt[tk.bucket_base + bkt[r][e]], 1u);
-    }
-  }
-  if (local) {  // this block's places: one global atomic per bucket it uses
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += kBigKeyThreads) {
-      const uint32_t h = hist[i];
-      if (h) hist[i] = atomicAdd(&cnt[tk.bucket_base + i], h);
+      for (int e = 0; e < 4; ++e)
+        if (xv[e] > 0) {
+          bkt[e] = key_bucket(kk[e], nb);
+          pos[e] = atomicAdd(&hist[bkt[e]], 1u);
+        }
     }
     __syncthreads();
-  }
+    chunk_scan(hist, (int)nb, red);
+    for (uint32_t i = tid; i <= nb; i += kBigKeyThreads) o[i] = hist[i];
 #pragma unroll
-  for (int r = 0; r < kBigKeyGroups; ++r) {
-    const int j0 = 4 * (ch.first / 4 + r * kBigKeyThreads + (int)threadIdx.x);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (pos[r][e] == 0xFFFFFFFFu) continue;
-      const uint32_t at = local ? hist[bkt[r][e]] + pos[r][e] : pos[r][e];
-      const unsigned long long ent = ((unsigned long long)kk[r][e] << 32) | (unsigned)(j0 + e);
-      if (at < (uint32_t)tk.cap) {
-        region[tk.region_base + (int64_t)bkt[r][e] * tk.cap + at] = ent;
-      } else {
-        const uint32_t q = atomicAdd(&ovf_cnt[ch.task], 1u);
-        ovf[tk.tmp_base + q] = ent;
+    for (int e = 0; e < 4; ++e)
+      if (pos[e] != 0xFFFFFFFFu) {
+        const int64_t at = seg + hist[bkt[e]] + pos[e];
+        ekey[at] = ((unsigned long long)kk[e] << 32) | (uint32_t)(j0 + e);
+        exi[at] = xv[e];
+        ev[at] = vv[e];
       }
-    }
+    return;
+  }
+  // several groups per thread: count, then recompute the keys and place
+  for (int j0 = first + 4 * tid; j0 < last; j0 += 4 * kBigKeyThreads) {
+    long long xv[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (j0 + e < last) xv[e] = tk.xi[j0 + e];
+    const uint4 w = philox(make_uint4((uint32_t)(j0 >> 2), (uint32_t)tk.cell, s, 2u * u),
+                           dp->seed_lo, dp->seed_hi);
+    const uint32_t kk[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (xv[e] > 0) atomicAdd(&hist[key_bucket(kk[e], nb)], 1u);
+  }
+  __syncthreads();
+  chunk_scan(hist, (int)nb, red);
+  for (uint32_t i = tid; i <= nb; i += kBigKeyThreads) o[i] = hist[i];
+  __syncthreads();  // the starts are read before they turn into cursors
+  for (int j0 = first + 4 * tid; j0 < last; j0 += 4 * kBigKeyThreads) {
+    long long xv[4] = {0, 0, 0, 0};
+    double vv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (j0 + e < last) {
+        xv[e] = tk.xi[j0 + e];
+        vv[e] = tk.v[j0 + e];
+      }
+    const uint4 w = philox(make_uint4((uint32_t)(j0 >> 2), (uint32_t)tk.cell, s, 2u * u),
+                           dp->seed_lo, dp->seed_hi);
+    const uint32_t kk[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (xv[e] > 0) {
+        const int64_t at = seg + atomicAdd(&hist[key_bucket(kk[e], nb)], 1u);
+        ekey[at] = ((unsigned long long)kk[e] << 32) | (uint32_t)(j0 + e);
+        exi[at] = xv[e];
+        ev[at] = vv[e];
+      }
   }
 }
 
 struct alignas(16) BigLds {
-  unsigned long long ent[kBigSortCap];  // the bucket's entries (unordered)
-  uint32_t sc[kBigSortCap + 4];         // sub-bucket counters / starts
-  uint32_t ord[kBigSortCap];            // slots in permutation order
-  // colliding pairs of one round of kBigThreads pairs: slots j, k (the
-  // larger multiplicity first), g, equal split
+  unsigned long long ent[kBigSortCap];  // keys in sub-bucket order
+  long long exi[kBigSortCap];           // gathered multiplicities, volumes, slots
+  double ev[kBigSortCap];
+  uint32_t slot[kBigSortCap];
+  uint32_t sc[kBigSortCap + 4];  // sub-bucket counters / starts
+  uint32_t ord[kBigSortCap];     // gathered entries in permutation order
+  // gathered index -> chunk, for this bucket and for the partner's bucket
+  uint16_t own[kBigSortCap], own1[kBigSortCap];
+  // per chunk: first gathered index (exclusive scan) and segment start, of
+  // this bucket (cs, cb) and of the bucket that holds the partner (cs1, cb1)
+  uint32_t cs[kBigMaxChunks + 1], cb[kBigMaxChunks];
+  uint32_t cs1[kBigMaxChunks + 1], cb1[kBigMaxChunks];
+  // colliding pairs of one round of kBigThreads pairs (attribute updates):
+  // slots j, k (the larger multiplicity first), g, equal split
   uint32_t lj[kBigThreads], lk[kBigThreads], lsplit[kBigThreads];
   long long lg[kBigThreads];
   int nlist;
   int red[kBigThreads / 64][4];
   unsigned long long red64[kBigThreads / 64];
-  uint32_t next_slot;  // partner of the last entry (next bucket's smallest)
+  unsigned long long pkey;  // partner of the last entry: the next bucket's smallest entry
+  long long pxi;
+  double pv;
 };
 
-// exclusive scan of L.sc[0, n) in place (n <= kBigSortCap), L.sc[n] = total;
-// kBigThreads threads, 4 counters each, fixed order
-__device__ __forceinline__ void big_scan(BigLds& L, int n) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int first = 4 * tid;
-  uint32_t c4[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-  for (int e = 0; e < 4; ++e) c4[e] = first + e < n ? L.sc[first + e] : 0u;
-  const int local = (int)(c4[0] + c4[1] + c4[2] + c4[3]);
-  int run = wave_excl_scan(local, lane);
-  if (lane == 63) L.red[wv][3] = run + local;
+// exclusive scan of one value per thread over the workgroup (fixed order)
+__device__ __forceinline__ int block_excl_scan(BigLds& L, int x, int& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int e = wave_excl_scan(x, lane);
+  if (lane == 63) L.red[wv][0] = e + x;
   __syncthreads();
-  for (int k = 0; k < wv; ++k) run += L.red[k][3];
-  if (tid == kBigThreads - 1) L.sc[n] = (uint32_t)(run + local);
+  total = 0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    if (first + e < n) L.sc[first + e] = (uint32_t)run;
-    run += (int)c4[e];
+  for (int k = 0; k < kBigThreads / 64; ++k) {
+    e += k < wv ? L.red[k][0] : 0;
+    total += L.red[k][0];
   }
   __syncthreads();
+  return e;
 }
 
-// block-wide sums of two values (fixed order)
+// workgroup sums of two values (fixed order)
 __device__ __forceinline__ void block_sum2(BigLds& L, int& a, int& b) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   a = wave_sum(a);
   b = wave_sum(b);
   if (lane == 0) {
-    L.red[wv][0] = a;
-    L.red[wv][1] = b;
+    L.red[wv][1] = a;
+    L.red[wv][2] = b;
   }
   __syncthreads();
   a = b = 0;
 #pragma unroll
   for (int k = 0; k < kBigThreads / 64; ++k) {
-    a += L.red[k][0];
-    b += L.red[k][1];
+    a += L.red[k][1];
+    b += L.red[k][2];
   }
   __syncthreads();
 }
 
-// The smallest entry of bucket nbk (its region part and its overflow entries).
-__device__ unsigned long long bucket_min(const BigTask& tk, const uint32_t* cnt,
-                                         const uint32_t* ovf_cnt, int task,
-                                         const unsigned long long* region,
-                                         const unsigned long long* ovf, int nbk, BigLds& L) {
-  const uint32_t len = cnt[tk.bucket_base + nbk];
-  const uint32_t in_reg = min(len, (uint32_t)tk.cap);
-  unsigned long long m = ~0ull;
-  for (uint32_t i = threadIdx.x; i < in_reg; i += kBigThreads)
-    m = min(m, region[tk.region_base + (int64_t)nbk * tk.cap + i]);
-  if (len > (uint32_t)tk.cap) {
-    const uint32_t no = ovf_cnt[task];
-    for (uint32_t i = threadIdx.x; i < no; i += kBigThreads) {
-      const unsigned long long e = ovf[tk.tmp_base + i];
-      if ((int)key_bucket((uint32_t)(e >> 32), (uint32_t)tk.nb) == nbk) m = min(m, e);
-    }
+// chunk of gathered index t: the last chunk i with cs[i] <= t (cs[0] = 0 <= t
+// < cs[n])
+__device__ __forceinline__ int chunk_of(const uint32_t* cs, int n, int t) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int)cs[mid] <= t) lo = mid;
+    else hi = mid;
   }
-  // block min
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const unsigned long long t = __shfl_xor(m, o);
-    m = min(m, t);
-  }
-  if (lane == 0) L.red64[wv] = m;
-  __syncthreads();
-  unsigned long long r = ~0ull;
-#pragma unroll
-  for (int k = 0; k < kBigThreads / 64; ++k) r = min(r, L.red64[k]);
-  __syncthreads();
-  return r;
+  return lo;
 }
 
 // ADAPT: the first pass of an adaptive substep; instead of drawing the
@@ -1308,23 +1343,18 @@ __device__ unsigned long long bucket_min(const BigTask& tk, const uint32_t* cnt,
 template <bool ADAPT>
 __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
     const SimDesc* __restrict__ descs, const BigTask* __restrict__ big,
-    const BigBucket* __restrict__ buckets, uint32_t* __restrict__ cnt,
-    uint32_t* __restrict__ ovf_cnt, uint32_t* __restrict__ cnt_next,
-    uint32_t* __restrict__ ovf_cnt_next, const unsigned long long* __restrict__ region,
-    const unsigned long long* __restrict__ ovf, uint32_t* __restrict__ gord, uint32_t k_abs,
-    BigAdapt* __restrict__ astate, unsigned long long* __restrict__ apmax,
-    double* __restrict__ apre, unsigned long long* __restrict__ apair) {
+    const BigBucket* __restrict__ buckets, const uint32_t* __restrict__ offs,
+    const unsigned long long* __restrict__ ekey, const long long* __restrict__ exi,
+    const double* __restrict__ ev, unsigned long long* __restrict__ skey,
+    uint32_t* __restrict__ gord, uint32_t k_abs, BigAdapt* __restrict__ astate,
+    unsigned long long* __restrict__ apmax, double* __restrict__ apre,
+    unsigned long long* __restrict__ apair) {
   __shared__ BigLds L;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const BigBucket bk = buckets[blockIdx.x];
   const BigTask tk = big[bk.task];
+  const SimDesc* dp = descs + bk.sim;
   const int b = bk.bucket;
-  // the other set of counters is cleared for the next step, skipped or not
-  if (tid == 0) {
-    cnt_next[tk.bucket_base + b] = 0;
-    if (b == 0) ovf_cnt_next[bk.task] = 0;
-  }
-  const SimDesc* dp = descs + tk.sim;
   const uint32_t s = k_abs + dp->step_delta;
   if (s >= dp->step_limit) return;
   double q_left = 0.0;
@@ -1333,17 +1363,24 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
     if (as.done) return;
     q_left = as.dt_left / dp->dv;
   }
-  const int nb = tk.nb;
-  // this bucket's start and the cell's live count
-  int before = 0, total = 0;
-  for (int i = tid; i < nb; i += kBigThreads) {
-    const int c_ = (int)cnt[tk.bucket_base + i];
-    before += i < b ? c_ : 0;
-    total += c_;
+  const int nb = tk.nb, nch = tk.n_chunks;
+  const int64_t tb = tk.tmp_base;
+  // this thread's chunk: its offsets of buckets b, b + 1, b + 2 and its live count
+  uint32_t o_b = 0, o_b1 = 0, o_b2 = 0;
+  int before = 0, tot = 0;
+  if (tid < nch) {
+    const uint32_t* oc = offs + tk.off_base + (int64_t)tid * (nb + 1);
+    o_b = oc[b];
+    o_b1 = oc[b + 1];
+    o_b2 = oc[min(b + 2, nb)];
+    tot = (int)oc[nb];
+    before = (int)o_b;
   }
-  block_sum2(L, before, total);
-  const int nlive = total, start = before;
-  const int len = (int)cnt[tk.bucket_base + b];
+  const int lb = (int)(o_b1 - o_b);
+  int len = 0;
+  const int e0 = block_excl_scan(L, lb, len);
+  block_sum2(L, before, tot);
+  const int start = before, nlive = tot;
   const int P = nlive >> 1;
   const int c = tk.cell;
   if (ADAPT && b == 0 && tid == 0) astate[bk.task].nlive = nlive;
@@ -1354,31 +1391,135 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
       sink[sink_base + 2 * m] = -1;
       sink[sink_base + 2 * m + 1] = -1;
     }
-  if (tid == 0) L.nlist = 0;
   // first entry whose pair this bucket takes, and whether any pair is taken
   const int i0 = start & 1;
   const bool any_pair = len > i0 && (start + i0) / 2 < P;
-  const bool fast = len <= tk.cap && len <= kBigSortCap;
-  uint32_t* gsorted = gord + tk.tmp_base + start;  // slow path: slots in order
+  const bool need_next = any_pair && ((start + len) & 1) && (start + len - 1) / 2 < P;
+  const bool fast = len <= min(tk.sort_cap, kBigSortCap);
+  uint32_t* gsorted = gord + tb + start;  // slow path: slots in order
+  if (tid == 0) L.nlist = 0;
   if (any_pair) {
+    // the partner's bucket: b + 1, else the next non-empty one
+    int len1 = 0, e1 = 0;
+    uint32_t p_lo = o_b1;
+    int l1 = tid < nch ? (int)(o_b2 - o_b1) : 0;
+    if (need_next) {
+      e1 = block_excl_scan(L, l1, len1);
+      for (int nbk = b + 2; len1 == 0 && nbk < nb; ++nbk) {
+        uint32_t hi = 0;
+        p_lo = 0;
+        if (tid < nch) {
+          const uint32_t* oc = offs + tk.off_base + (int64_t)tid * (nb + 1);
+          p_lo = oc[nbk];
+          hi = oc[nbk + 1];
+        }
+        l1 = (int)(hi - p_lo);
+        e1 = block_excl_scan(L, l1, len1);
+      }
+    }
+    // per chunk: where its entries start, and which gathered indices it holds
+    if (tid < nch) {
+      L.cs[tid] = (uint32_t)e0;
+      L.cb[tid] = o_b;
+      L.cs1[tid] = (uint32_t)e1;
+      L.cb1[tid] = p_lo;
+      if (fast)
+        for (int k = 0; k < lb; ++k) L.own[e0 + k] = (uint16_t)tid;
+      if (need_next)
+        for (int k = 0; k < l1 && e1 + k < kBigSortCap; ++k) L.own1[e1 + k] = (uint16_t)tid;
+    }
+    if (tid == 0) {
+      L.cs[nch] = (uint32_t)len;
+      L.cs1[nch] = (uint32_t)len1;
+    }
+    __syncthreads();
+    // one round of loads: the bucket's entries (fast path) and the partner
+    // bucket's first kBigSortCap entries
+    unsigned long long me[kBigPer], pk[kBigPer];
+    long long mx[kBigPer], px[kBigPer];
+    double mv[kBigPer], pv[kBigPer];
+#pragma unroll
+    for (int r = 0; r < kBigPer; ++r) {
+      const int t = r * kBigThreads + tid;
+      me[r] = 0;
+      mx[r] = 0;
+      mv[r] = 0.0;
+      if (fast && t < len) {
+        const int i = L.own[t];
+        const int64_t src = tb + (int64_t)i * tk.chunk_slots + L.cb[i] + (t - (int)L.cs[i]);
+        me[r] = ekey[src];
+        mx[r] = exi[src];
+        mv[r] = ev[src];
+      }
+      pk[r] = ~0ull;
+      px[r] = 0;
+      pv[r] = 0.0;
+      if (need_next && t < len1) {
+        const int i = L.own1[t];
+        const int64_t src = tb + (int64_t)i * tk.chunk_slots + L.cb1[i] + (t - (int)L.cs1[i]);
+        pk[r] = ekey[src];
+        px[r] = exi[src];
+        pv[r] = ev[src];
+      }
+    }
+    if (need_next) {  // the partner: the smallest entry of its bucket
+      unsigned long long m = ~0ull;
+      long long mxx = 0;
+      double mvv = 0.0;
+#pragma unroll
+      for (int r = 0; r < kBigPer; ++r)
+        if (pk[r] < m) {
+          m = pk[r];
+          mxx = px[r];
+          mvv = pv[r];
+        }
+      for (int t = kBigSortCap + tid; t < len1; t += kBigThreads) {  // a long partner bucket
+        const int i = chunk_of(L.cs1, nch, t);
+        const int64_t src = tb + (int64_t)i * tk.chunk_slots + L.cb1[i] + (t - (int)L.cs1[i]);
+        const unsigned long long k = ekey[src];
+        if (k < m) {
+          m = k;
+          mxx = exi[src];
+          mvv = ev[src];
+        }
+      }
+      unsigned long long w = m;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) w = min(w, (unsigned long long)__shfl_xor(w, o));
+      if (lane == 0) L.red64[wv] = w;
+      __syncthreads();
+      unsigned long long r = ~0ull;
+#pragma unroll
+      for (int k = 0; k < kBigThreads / 64; ++k) r = min(r, L.red64[k]);
+      if (m == r && r != ~0ull) {  // entries are distinct: one thread holds it
+        L.pkey = m;
+        L.pxi = mxx;
+        L.pv = mvv;
+      }
+    }
     if (fast) {
-      // order the entries in LDS: sub-buckets on the key's place inside
-      // this bucket's key range, then an exact rank inside each sub-bucket
+      // order in LDS: sub-buckets on the key's place inside this bucket's key
+      // range, then an exact rank inside each sub-bucket
       const int sbits = len <= 1 ? 0 : 32 - __clz(len - 1);
       const int nsb = 1 << sbits;
       // scale < 2^(31 + 10): the product with a 32-bit key needs 128 bits
       const unsigned long long scale = (unsigned long long)(uint32_t)nb << sbits;
       for (int i = tid; i < nsb + 1; i += kBigThreads) L.sc[i] = 0;
-      constexpr int PER = kBigSortCap / kBigThreads;
-      unsigned long long me[PER];
-      uint32_t sub[PER], pos[PER];
+      uint32_t sub[kBigPer], pos[kBigPer];
+#pragma unroll
+      for (int r = 0; r < kBigPer; ++r) {
+        const int t = r * kBigThreads + tid;
+        if (t < len) {
+          L.exi[t] = mx[r];
+          L.ev[t] = mv[r];
+          L.slot[t] = (uint32_t)(me[r] & 0xFFFFFFFFull);
+        }
+      }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int i = r * kBigThreads + tid;
-        me[r] = 0;
-        if (i < len) {
-          me[r] = region[tk.region_base + (int64_t)b * tk.cap + i];
+      for (int r = 0; r < kBigPer; ++r) {
+        const int t = r * kBigThreads + tid;
+        if (t < len) {
           // monotone in the key: (key nb 2^sbits) >> 32 = b 2^sbits + sub
           const unsigned long long key = me[r] >> 32;
           const unsigned long long lo = key * scale, hi = __umul64hi(key, scale);
@@ -1387,13 +1528,27 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
         }
       }
       __syncthreads();
-      big_scan(L, nsb);
-      uint32_t st[PER], ln[PER];
+      int tot_sc = 0;
+      {  // exclusive scan of the sub-bucket counters (4 per thread)
+        const int f = 4 * tid;
+        uint32_t c4[4];
 #pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int i = r * kBigThreads + tid;
+        for (int e = 0; e < 4; ++e) c4[e] = f + e < nsb ? L.sc[f + e] : 0u;
+        int run = block_excl_scan(L, (int)(c4[0] + c4[1] + c4[2] + c4[3]), tot_sc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (f + e < nsb) L.sc[f + e] = (uint32_t)run;
+          run += (int)c4[e];
+        }
+        if (tid == 0) L.sc[nsb] = (uint32_t)tot_sc;
+      }
+      __syncthreads();
+      uint32_t st[kBigPer], ln[kBigPer];
+#pragma unroll
+      for (int r = 0; r < kBigPer; ++r) {
+        const int t = r * kBigThreads + tid;
         st[r] = ln[r] = 0;
-        if (i < len) {
+        if (t < len) {
           st[r] = L.sc[sub[r]];
           ln[r] = L.sc[sub[r] + 1] - st[r];
           L.ent[st[r] + pos[r]] = me[r];
@@ -1401,56 +1556,56 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
       }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int i = r * kBigThreads + tid;
-        if (i < len) {
+      for (int r = 0; r < kBigPer; ++r) {
+        const int t = r * kBigThreads + tid;
+        if (t < len) {
           uint32_t rk = st[r];
           for (uint32_t k = 0; k < ln[r]; ++k) rk += L.ent[st[r] + k] < me[r] ? 1u : 0u;
-          L.ord[rk] = (uint32_t)(me[r] & 0xFFFFFFFFull);
+          L.ord[rk] = (uint32_t)t;
         }
       }
     } else {  // slow path: rank every entry against the whole bucket in global memory
       if (tid == 0) atomicOr(dp->status, kFlagBucketOverflow);
-      const int in_reg = min(len, tk.cap);
-      const uint32_t no = len > tk.cap ? ovf_cnt[bk.task] : 0u;
-      const unsigned long long* reg = region + tk.region_base + (int64_t)b * tk.cap;
-      const unsigned long long* ov = ovf + tk.tmp_base;
-      auto rank_of = [&](unsigned long long e) {
-        uint32_t rk = 0;
-        for (int k = 0; k < in_reg; ++k) rk += reg[k] < e ? 1u : 0u;
-        for (uint32_t k = 0; k < no; ++k) {
-          const unsigned long long f = ov[k];
-          if ((int)key_bucket((uint32_t)(f >> 32), (uint32_t)nb) == b && f < e) ++rk;
-        }
-        return rk;
-      };
-      for (int i = tid; i < in_reg; i += kBigThreads) {
-        const unsigned long long e = reg[i];
-        gsorted[rank_of(e)] = (uint32_t)(e & 0xFFFFFFFFull);
+      unsigned long long* sk = skey + tb + start;
+      for (int t = tid; t < len; t += kBigThreads) {
+        const int i = chunk_of(L.cs, nch, t);
+        sk[t] = ekey[tb + (int64_t)i * tk.chunk_slots + L.cb[i] + (t - (int)L.cs[i])];
       }
-      for (uint32_t i = tid; i < no; i += kBigThreads) {
-        const unsigned long long e = ov[i];
-        if ((int)key_bucket((uint32_t)(e >> 32), (uint32_t)nb) == b)
-          gsorted[rank_of(e)] = (uint32_t)(e & 0xFFFFFFFFull);
+      __threadfence_block();
+      __syncthreads();
+      for (int t = tid; t < len; t += kBigThreads) {
+        const unsigned long long e = sk[t];
+        uint32_t rk = 0;
+        for (int k = 0; k < len; ++k) rk += sk[k] < e ? 1u : 0u;
+        gsorted[rk] = (uint32_t)(e & 0xFFFFFFFFull);
       }
       __threadfence_block();
     }
-    // partner of the last entry: the smallest entry of the next non-empty bucket
-    if (((start + len) & 1) && (start + len - 1) / 2 < P) {
-      int nbk = b + 1;
-      while (nbk < nb && cnt[tk.bucket_base + nbk] == 0) ++nbk;
-      unsigned long long m = ~0ull;
-      if (nbk < nb) m = bucket_min(tk, cnt, ovf_cnt, bk.task, region, ovf, nbk, L);
-      if (tid == 0) L.next_slot = (uint32_t)(m & 0xFFFFFFFFull);
-    }
   }
   __syncthreads();
-  // pairs: positions start + i with i = i0, i0 + 2, ...; rounds of
-  // kBigThreads pairs, each followed by the dense update of its collisions
-  int ncoll = 0;
-  const double S = (double)((nlive & 1) ? nlive : nlive - 1);
+  // the i-th entry of the bucket's order (i == len: the partner)
   int64_t* xi = tk.xi;
   double* v = tk.v;
+  auto fetch = [&](int i, int& slot, long long& x, double& vol) {
+    if (i == len) {
+      slot = (int)(uint32_t)(L.pkey & 0xFFFFFFFFull);
+      x = L.pxi;
+      vol = L.pv;
+    } else if (fast) {
+      const int g = (int)L.ord[i];
+      slot = (int)L.slot[g];
+      x = L.exi[g];
+      vol = L.ev[g];
+    } else {
+      slot = (int)gsorted[i];
+      x = xi[slot];
+      vol = v[slot];
+    }
+  };
+  // pairs: positions start + i with i = i0, i0 + 2, ...; rounds of
+  // kBigThreads pairs, each followed by the attribute updates of its collisions
+  int ncoll = 0;
+  const double S = (double)((nlive & 1) ? nlive : nlive - 1);
   const int64_t o0 = tk.xi - dp->xi;
   const int npairs = any_pair ? min((len - i0 + 1) >> 1, P - ((start + i0) >> 1)) : 0;
   if (ADAPT) {  // pre-products, pairs and this bucket's largest p at the remaining time
@@ -1458,17 +1613,18 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
     for (int t = tid; t < npairs; t += kBigThreads) {
       const int i = i0 + 2 * t;
       const int m = (start + i) >> 1;
-      const int a = (int)(fast ? L.ord[i] : gsorted[i]);
-      const int bb = (int)(i + 1 < len ? (fast ? L.ord[i + 1] : gsorted[i + 1]) : L.next_slot);
-      const long long xa = xi[a], xb = xi[bb];
-      const double kv = coal_kernel(dp->kernel, dp->b, v[a], v[bb]);
+      int a, bb;
+      long long xa, xb;
+      double va, vb;
+      fetch(i, a, xa, va);
+      fetch(i + 1, bb, xb, vb);
+      const double kv = coal_kernel(dp->kernel, dp->b, va, vb);
       const double pp = ((double)(xa > xb ? xa : xb) * kv) * S;
-      apre[tk.tmp_base + m] = pp;
-      apair[tk.tmp_base + m] = (unsigned long long)(uint32_t)a | ((unsigned long long)bb << 32);
+      apre[tb + m] = pp;
+      apair[tb + m] = (unsigned long long)(uint32_t)a | ((unsigned long long)bb << 32);
       pm = fmax(pm, pp * q_left);
     }
     // largest p of the block; p >= 0, so its bits order like the values
-    const int lane = tid & 63, wv = tid >> 6;
     unsigned long long pb = (unsigned long long)__double_as_longlong(pm);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) pb = max(pb, (unsigned long long)__shfl_xor(pb, o));
@@ -1482,15 +1638,18 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
     }
     return;
   }
+  const int A = dp->n_attr;
   for (int base = 0; base < npairs; base += kBigThreads) {
     const int t = base + tid;
     if (t < npairs) {
       const int i = i0 + 2 * t;
       const int m = (start + i) >> 1;
-      const int a = (int)(fast ? L.ord[i] : gsorted[i]);
-      const int bb = (int)(i + 1 < len ? (fast ? L.ord[i + 1] : gsorted[i + 1]) : L.next_slot);
-      const long long xa = xi[a], xb = xi[bb];
-      const double kv = coal_kernel(dp->kernel, dp->b, v[a], v[bb]);
+      int a, bb;
+      long long xa, xb;
+      double va, vb;
+      fetch(i, a, xa, va);
+      fetch(i + 1, bb, xb, vb);
+      const double kv = coal_kernel(dp->kernel, dp->b, va, vb);
       const double p = (((double)(xa > xb ? xa : xb) * kv) * S) * dp->q;
       const uint4 w = philox(make_uint4((uint32_t)(m >> 1), (uint32_t)c, s, 1u), dp->seed_lo,
                              dp->seed_hi);
@@ -1500,10 +1659,11 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
         sink[sink_base + 2 * m] = (int64_t)((uint64_t)a | ((uint64_t)bb << 32));
         sink[sink_base + 2 * m + 1] = gamma;
       }
-      if (gamma > 0) {  // multiplicities now, volumes and attributes listed
+      if (gamma > 0) {  // multiplicities and volumes now, attributes listed
         ++ncoll;
         const bool a_is_j = xa >= xb;  // ties: the pair's first member
         const long long xj = a_is_j ? xa : xb, xk = a_is_j ? xb : xa;
+        const double vj = a_is_j ? va : vb, vk = a_is_j ? vb : va;
         long long g = gamma;
         if (g > 1) {
           const long long ratio = xj / xk;
@@ -1511,50 +1671,56 @@ __global__ void __launch_bounds__(kBigThreads) k_big_bucket(
         }
         const int j = a_is_j ? a : bb, k = a_is_j ? bb : a;
         const long long rest = xj - g * xk;
+        const double vn = fma((double)g, vj, vk);
         uint32_t split = 0;
+        v[k] = vn;
         if (rest > 0) {
           xi[j] = rest;
         } else {  // equal-multiplicity split
           const long long h = xk >> 1;
           xi[j] = h;
           xi[k] = xk - h;
+          v[j] = vn;
           split = 1;
         }
-        const int at = atomicAdd(&L.nlist, 1);
-        L.lj[at] = (uint32_t)j;
-        L.lk[at] = (uint32_t)k;
-        L.lsplit[at] = split;
-        L.lg[at] = g;
+        if (A > 0) {
+          const int at = atomicAdd(&L.nlist, 1);
+          L.lj[at] = (uint32_t)j;
+          L.lk[at] = (uint32_t)k;
+          L.lsplit[at] = split;
+          L.lg[at] = g;
+        }
       }
     }
-    __syncthreads();
-    const int nl = L.nlist;
-    const int F = 1 + dp->n_attr;
-    for (int u = tid; u < nl * F; u += kBigThreads) {  // one round of loads
-      const int li = u / F, f = u - li * F;
-      const int j = (int)L.lj[li], k = (int)L.lk[li];
-      double* X = f == 0 ? v : dp->attrs + (int64_t)(f - 1) * dp->n_slots + o0;
-      const double val = fma((double)L.lg[li], X[j], X[k]);
-      X[k] = val;
-      if (L.lsplit[li]) X[j] = val;
+    if (A > 0) {  // attributes of the listed pairs: one round of loads
+      __syncthreads();
+      const int nl = L.nlist;
+      for (int q = tid; q < nl * A; q += kBigThreads) {
+        const int li = q / A, f = q - li * A;
+        const int j = (int)L.lj[li], k = (int)L.lk[li];
+        double* X = dp->attrs + (int64_t)f * dp->n_slots + o0;
+        const double val = fma((double)L.lg[li], X[j], X[k]);
+        X[k] = val;
+        if (L.lsplit[li]) X[j] = val;
+      }
+      __syncthreads();
+      if (tid == 0) L.nlist = 0;
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) L.nlist = 0;
-    __syncthreads();
   }
   ncoll = wave_sum(ncoll);
-  if ((tid & 63) == 0) L.red[tid >> 6][2] = ncoll;
+  if ((tid & 63) == 0) L.red[tid >> 6][3] = ncoll;
   __syncthreads();
   if (tid == 0) {
-    int tot = 0;
+    int tc = 0;
 #pragma unroll
-    for (int k = 0; k < kBigThreads / 64; ++k) tot += L.red[k][2];
-    unsigned long long* st = dp->stats + (blockIdx.x % kStatSlots) * kStatFields;
-    if (tot) atomicAdd(st + 1, (unsigned long long)tot);
+    for (int k = 0; k < kBigThreads / 64; ++k) tc += L.red[k][3];
+    unsigned long long* stt = dp->stats + (blockIdx.x % kStatSlots) * kStatFields;
+    if (tc) atomicAdd(stt + 1, (unsigned long long)tc);
     if (b == 0) {  // once per cell and step
-      atomicAdd(st + 0, (unsigned long long)nlive);
-      atomicAdd(st + 2, 1ull);
-      atomicAdd(st + 3, 1ull);
+      atomicAdd(stt + 0, (unsigned long long)nlive);
+      atomicAdd(stt + 2, 1ull);
+      atomicAdd(stt + 3, 1ull);
     }
   }
 }
@@ -1732,77 +1898,132 @@ __global__ void k_abig_active(const BigAdapt* __restrict__ st, const int* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Moments: one block of 256 per cell, fixed-order tree reductions
+// Moments: one workgroup of W waves per cell, one pass over the cell's slots.
+// Each thread accumulates its slots (strided by the workgroup) in order; the
+// spectrum bin of a slot is found by bisection of the edges staged in LDS,
+// and each wave adds its slots of one tile into per-wave bin sums in LDS,
+// bin by bin (a wave reduction per bin present in the tile).  Waves are
+// combined in a fixed order, so every sum has a fixed reduction order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum(double x, double* red) {
-  red[threadIdx.x] = x;
-  __syncthreads();
-  for (int st = 128; st >= 1; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
+constexpr int kMomentsMaxAttr = 16;
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+  x += dpp_d<kDppQuad1032>(x);
+  x += dpp_d<kDppQuad2301>(x);
+  x += dpp_d<kDppHalfMirror>(x);
+  x += dpp_d<kDppRowMirror>(x);
+  return ((readlane_d(x, 15) + readlane_d(x, 31)) + readlane_d(x, 47)) + readlane_d(x, 63);
 }
 
-__global__ void __launch_bounds__(256) k_moments(SimDesc d, int64_t* m0, double* m12,
-                                                 double* attr_sums, const double* edges,
-                                                 int n_bins, double* spectrum) {
-  __shared__ double red[256];
-  __shared__ unsigned long long ired[256];
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += (unsigned long long)__shfl_xor(x, o);
+  return x;
+}
+
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_moments(SimDesc d, int64_t* m0, double* m12,
+                                                    double* attr_sums, const double* edges,
+                                                    int n_bins, double* spectrum) {
+  extern __shared__ double mom_lds[];  // edges[n_bins + 1], then W x n_bins bin sums
+  __shared__ double red_d[W][2 + kMomentsMaxAttr];
+  __shared__ unsigned long long red_u[W];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c = blockIdx.x;
   const int64_t o0 = d.cell_off[c];
-  const int64_t n = d.cell_off[c + 1] - o0;
-  unsigned long long cnt = 0;
-  double s1 = 0.0, s2 = 0.0;
-  for (int64_t j = threadIdx.x; j < n; j += 256) {
-    const long long x = d.xi[o0 + j];
-    if (x > 0) {
-      const double w1 = (double)x * d.v[o0 + j];
-      cnt += (unsigned long long)x;
-      s1 += w1;
-      s2 += w1 * d.v[o0 + j];
-    }
-  }
-  ired[threadIdx.x] = cnt;
-  __syncthreads();
-  for (int st = 128; st >= 1; st >>= 1) {
-    if ((int)threadIdx.x < st) ired[threadIdx.x] += ired[threadIdx.x + st];
+  const int n = (int)(d.cell_off[c + 1] - o0);
+  const int A = d.n_attr;
+  const bool spec = spectrum != nullptr && n_bins > 0;
+  double* e = mom_lds;
+  double* bins = mom_lds + (n_bins + 1);
+  if (spec) {
+    for (int k = tid; k <= n_bins; k += 64 * W) e[k] = edges[k];
+    for (int k = tid; k < W * n_bins; k += 64 * W) bins[k] = 0.0;
     __syncthreads();
   }
-  if (threadIdx.x == 0 && m0) m0[c] = (int64_t)ired[0];
-  s1 = block_sum(s1, red);
-  s2 = block_sum(s2, red);
-  if (threadIdx.x == 0 && m12) {
-    m12[2 * c] = s1;
-    m12[2 * c + 1] = s2;
-  }
-  if (attr_sums) {
-    for (int q = 0; q < d.n_attr; ++q) {
-      const double* a = d.attrs + (int64_t)q * d.n_slots + o0;
-      double sa = 0.0;
-      for (int64_t j = threadIdx.x; j < n; j += 256) {
-        const long long x = d.xi[o0 + j];
-        if (x > 0) sa += (double)x * a[j];
+  unsigned long long cnt = 0;
+  double s1 = 0.0, s2 = 0.0;
+  double sa[kMomentsMaxAttr];
+#pragma unroll
+  for (int q = 0; q < kMomentsMaxAttr; ++q) sa[q] = 0.0;
+  const double lo = spec ? e[0] : 0.0, hi = spec ? e[n_bins] : 0.0;
+  // tiles of 64 W slots; every wave runs every tile (uniform trip count)
+  for (int base = 0; base < n; base += 64 * W) {
+    const int j = base + tid;
+    long long x = 0;
+    double vv = 0.0;
+    if (j < n) x = d.xi[o0 + j];
+    if (x > 0) vv = d.v[o0 + j];
+    const double w1 = (double)x * vv;
+    if (x > 0) {
+      cnt += (unsigned long long)x;
+      s1 += w1;
+      s2 += w1 * vv;
+#pragma unroll
+      for (int q = 0; q < kMomentsMaxAttr; ++q)
+        if (q < A) sa[q] += (double)x * d.attrs[(int64_t)q * d.n_slots + o0 + j];
+    }
+    if (spec) {
+      int k = -1;
+      if (x > 0 && lo <= vv && vv < hi) {  // e[k] <= vv < e[k + 1]
+        int a = 0, b = n_bins;
+        while (b - a > 1) {
+          const int m = (a + b) >> 1;
+          if (e[m] <= vv) a = m;
+          else b = m;
+        }
+        k = a;
       }
-      sa = block_sum(sa, red);
-      if (threadIdx.x == 0) attr_sums[(int64_t)c * d.n_attr + q] = sa;
+      unsigned long long act = __ballot(k >= 0);
+      while (act) {
+        const int kk = __builtin_amdgcn_readlane(k, __ffsll((long long)act) - 1);
+        const bool mine = k == kk;
+        const double s = wave_sum_d(mine ? w1 : 0.0);
+        if (lane == 0) bins[wv * n_bins + kk] += s;
+        act &= ~__ballot(mine);
+      }
     }
   }
-  if (spectrum) {
-    for (int k = 0; k < n_bins; ++k) {
-      const double lo = edges[k], hi = edges[k + 1];
-      double sb = 0.0;
-      for (int64_t j = threadIdx.x; j < n; j += 256) {
-        const long long x = d.xi[o0 + j];
-        const double vv = d.v[o0 + j];
-        if (x > 0 && lo <= vv && vv < hi) sb += (double)x * vv;
-      }
-      sb = block_sum(sb, red);
-      if (threadIdx.x == 0) spectrum[(int64_t)c * n_bins + k] = sb;
+  cnt = wave_sum_u64(cnt);
+  s1 = wave_sum_d(s1);
+  s2 = wave_sum_d(s2);
+#pragma unroll
+  for (int q = 0; q < kMomentsMaxAttr; ++q)
+    if (q < A) sa[q] = wave_sum_d(sa[q]);
+  if (lane == 0) {
+    red_u[wv] = cnt;
+    red_d[wv][0] = s1;
+    red_d[wv][1] = s2;
+#pragma unroll
+    for (int q = 0; q < kMomentsMaxAttr; ++q)
+      if (q < A) red_d[wv][2 + q] = sa[q];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long tc = red_u[0];
+    double t1 = red_d[0][0], t2 = red_d[0][1];
+    for (int w = 1; w < W; ++w) {
+      tc += red_u[w];
+      t1 += red_d[w][0];
+      t2 += red_d[w][1];
+    }
+    if (m0) m0[c] = (int64_t)tc;
+    if (m12) {
+      m12[2 * c] = t1;
+      m12[2 * c + 1] = t2;
     }
   }
+  if (attr_sums && tid < A) {
+    double t = red_d[0][2 + tid];
+    for (int w = 1; w < W; ++w) t += red_d[w][2 + tid];
+    attr_sums[(int64_t)c * A + tid] = t;
+  }
+  if (spec)
+    for (int k = tid; k < n_bins; k += 64 * W) {
+      double t = bins[k];
+      for (int w = 1; w < W; ++w) t += bins[w * n_bins + k];
+      spectrum[(int64_t)c * n_bins + k] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2009,9 +2230,8 @@ static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st
                        p.mid_tasks[cls] + np, k_abs);
 }
 
-hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, uint32_t big_step,
-                       int nsteps, int waves_per_cell, hipStream_t st, const SideStream& side) {
-  const uint32_t k_abs0 = k_abs;
+hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
+                       int waves_per_cell, hipStream_t st, const SideStream& side) {
   // Two independent groups of launches run on two streams and fill each
   // other's tails: the cells of up to 256 slots and the mid-size cells on a
   // second stream, the 384- and 512-slot classes and the big-cell chain on
@@ -2039,14 +2259,13 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, uint32_t
   launch_class<512>(p, 4, k_abs, flip, nsteps, waves_per_cell, st);
   launch_class<384>(p, 3, k_abs, flip, nsteps, waves_per_cell, st);
   for (int t = 0; t < nsteps && p.n_chunks > 0; ++t) {  // big cells: two launches per step
-    const uint32_t k_abs = k_abs0 + t;
-    const uint32_t par = (big_step + (uint32_t)t) & 1u;
     hipLaunchKernelGGL(k_big_keys, dim3(p.n_chunks), dim3(kBigKeyThreads), 0, st, p.desc, p.big,
-                       p.chunks, p.cnt[par], p.ovf_cnt[par], p.region, p.ovf, k_abs,
+                       p.chunks, p.offs, p.ekey, p.exi, p.ev, k_abs + t,
                        (const BigAdapt*)nullptr);
     hipLaunchKernelGGL(k_big_bucket<false>, dim3(p.n_buckets), dim3(kBigThreads), 0, st, p.desc,
-                       p.big, p.buckets, p.cnt[par], p.ovf_cnt[par], p.cnt[par ^ 1u],
-                       p.ovf_cnt[par ^ 1u], p.region, p.ovf, p.ord, k_abs, (BigAdapt*)nullptr,
+                       p.big, p.buckets, (const uint32_t*)p.offs,
+                       (const unsigned long long*)p.ekey, (const long long*)p.exi,
+                       (const double*)p.ev, p.skey, p.ord, k_abs + t, (BigAdapt*)nullptr,
                        (unsigned long long*)nullptr, (double*)nullptr,
                        (unsigned long long*)nullptr);
   }
@@ -2062,16 +2281,16 @@ hipError_t launch_abig_init(const PlanDev& p, uint32_t k_abs, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_abig_round(const PlanDev& p, uint32_t k_abs, uint32_t round, uint32_t cnt_par,
-                             hipStream_t st) {
-  const uint32_t q = round & 1u, par = cnt_par & 1u;
+hipError_t launch_abig_round(const PlanDev& p, uint32_t k_abs, uint32_t round, hipStream_t st) {
+  const uint32_t q = round & 1u;
   hipLaunchKernelGGL(k_big_keys, dim3(p.n_achunks), dim3(kBigKeyThreads), 0, st, p.desc, p.big,
-                     p.achunks, p.cnt[par], p.ovf_cnt[par], p.region, p.ovf, k_abs,
+                     p.achunks, p.offs, p.ekey, p.exi, p.ev, k_abs,
                      (const BigAdapt*)p.astate[q]);
   hipLaunchKernelGGL(k_big_bucket<true>, dim3(p.n_abuckets), dim3(kBigThreads), 0, st, p.desc,
-                     p.big, p.abuckets, p.cnt[par], p.ovf_cnt[par], p.cnt[par ^ 1u],
-                     p.ovf_cnt[par ^ 1u], p.region, p.ovf, p.ord, k_abs, p.astate[q], p.apmax[q],
-                     p.apre, p.apair);
+                     p.big, p.abuckets, (const uint32_t*)p.offs,
+                     (const unsigned long long*)p.ekey, (const long long*)p.exi,
+                     (const double*)p.ev, p.skey, p.ord, k_abs, p.astate[q], p.apmax[q], p.apre,
+                     p.apair);
   hipLaunchKernelGGL(k_abig_pairs, dim3(p.n_apblocks), dim3(kAbigPairs), 0, st, p.desc, p.big,
                      p.apblocks, (const BigAdapt*)p.astate[q], p.astate[q ^ 1u],
                      (const unsigned long long*)p.apmax[q], p.apmax[q ^ 1u],
@@ -2086,12 +2305,19 @@ hipError_t launch_abig_active(const PlanDev& p, uint32_t round, uint32_t* count,
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const SimDesc& d, int n_cells, int64_t* m0, double* m12,
+hipError_t launch_moments(const SimDesc& d, int n_cells, int waves, int64_t* m0, double* m12,
                           double* attr_sums, const double* edges, int n_bins, double* spectrum,
                           hipStream_t st) {
   if (n_cells <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_moments, dim3(n_cells), dim3(256), 0, st, d, m0, m12, attr_sums, edges,
-                     n_bins, spectrum);
+  const size_t lds = spectrum && n_bins > 0
+                         ? sizeof(double) * ((size_t)n_bins + 1 + (size_t)waves * n_bins)
+                         : 0;
+  if (waves == 1)
+    hipLaunchKernelGGL(k_moments<1>, dim3(n_cells), dim3(64), lds, st, d, m0, m12, attr_sums,
+                       edges, n_bins, spectrum);
+  else
+    hipLaunchKernelGGL(k_moments<4>, dim3(n_cells), dim3(256), lds, st, d, m0, m12, attr_sums,
+                       edges, n_bins, spectrum);
   return hipGetLastError();
 }
 

@@ -45,6 +45,27 @@ def test_host_side_sizes_and_errors():
     assert B.sdm_strerror(B.SDM_ENOMEM) == "workspace too small"
 
 
+def test_workspace_bound_covers_big_cells():
+    """The layout-free workspace bound covers the exact size of layouts with
+    big cells of many sizes (one and several chunks, many buckets), and a cell
+    above 8 388 608 slots is an invalid layout."""
+    import numpy as np
+
+    from paper_2103_17238_amd import binding as B
+
+    n = 8388608
+    one = B.sdm_workspace_bytes(B.make_config(n, 1), [0, n])
+    assert 0 < one <= B.sdm_workspace_bytes(B.make_config(n, 1))
+    assert B.sdm_workspace_bytes(B.make_config(n + 1, 1), [0, n + 1]) == 0
+    assert B.sdm_workspace_bytes(B.make_config(n + 1, 2), [0, 1, n + 1]) > 0
+    for sizes in ([513, 600, 20000], [262144, 262145], [1 << 20, 3], [5000] * 7, [100] * 50):
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        for adaptive in (False, True):
+            cfg = B.make_config(int(off[-1]), len(sizes), n_attr=2, adaptive=adaptive)
+            exact = B.sdm_workspace_bytes(cfg, off)
+            assert 0 < exact <= B.sdm_workspace_bytes(cfg), (sizes, adaptive)
+
+
 def test_displace_argument_checks():
     """Argument errors of sdm_displace are caught on the host before any HIP
     call (fake device addresses are never dereferenced)."""

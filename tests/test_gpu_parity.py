@@ -144,12 +144,12 @@ def test_bucket_overflow_path_exact(B, orc):
 
 
 @pytest.mark.parametrize("target,cap", [(64, 48), (32, 8)])
-def test_big_cell_overflow_list_exact(B, orc, target, cap):
-    """Bucket regions smaller than the expected bucket size: most buckets
-    spill into the overflow list and are ordered in global memory (the slow
-    exact path, flagged); pairs and state still equal the oracle's."""
+def test_big_cell_small_sort_cap_exact(B, orc, target, cap):
+    """An LDS sort stage shorter than the expected bucket size: most buckets
+    are ranked in global memory (the slow exact path, flagged), the others in
+    LDS; pairs and state still equal the oracle's."""
     st = I.golovin_box(2 ** 15, seed=3)
-    say(f"big-cell overflow list target={target} cap={cap}")
+    say(f"big-cell slow path target={target} cap={cap}")
     g = GpuRun(B, st, sink=True, tuning=dict(big_bucket_target=target, big_bucket_cap=cap,
                                              mid_max_slots=0))
     o = st.copy()
@@ -162,6 +162,26 @@ def test_big_cell_overflow_list_exact(B, orc, target, cap):
         assert np.array_equal(g.log(), out["log"])
     assert B.sdm_status_word(g.sim.handle) & B.SDM_FLAG_BUCKET_OVERFLOW
     g.close()
+
+
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_sparse_big_cells_empty_buckets(B, orc, adaptive):
+    """Big cells of up to 20000 slots with 98 % dead slots and 32-SD buckets:
+    most buckets are empty, so the partner of a bucket's last entry sits
+    several buckets on; with attributes, bit-exact against the oracle."""
+    st = I.random_cells(12, 20000, n_attr=1, dead_fraction=0.98, rng_seed=41, p_boost=3e3)
+    st.adaptive = adaptive
+    say(f"sparse big cells adaptive={adaptive}")
+    assert _compare_run(B, orc, st, 6, tuning=dict(mid_max_slots=0, big_bucket_target=32),
+                        label=f"sparse-{adaptive}")
+
+
+def test_big_cell_several_key_groups(B, orc):
+    """A 2^19-SD cell: each key block takes several Philox groups per thread
+    (counted, then recomputed and placed); bit-exact with the pair log."""
+    st = I.golovin_box(2 ** 19, seed=5)
+    say("golovin box 2^19")
+    assert _compare_run(B, orc, st, 3, label="golovin-2^19")
 
 
 def test_big_golovin_box(B, orc):
@@ -437,12 +457,20 @@ def test_gamma_cap_flag(B, orc):
     g.close()
 
 
-def test_moments_parity(B, orc):
-    st = I.random_cells(50, 2000, n_attr=3, rng_seed=41)
+@pytest.mark.parametrize("case", ["wide", "narrow-1024-bins"])
+def test_moments_parity(B, orc, case):
+    """Moments and spectrum against the oracle: cells of up to 2000 slots (four
+    waves per cell) with 40 bins covering every SD, and cells of up to 300
+    slots (one wave per cell) with 1024 narrow bins that leave SDs outside."""
+    if case == "wide":
+        st = I.random_cells(50, 2000, n_attr=3, rng_seed=41)
+        ev = cf.volume_of_radius(cf.radius_edges(1e-6, 5e-3, 40))
+    else:
+        st = I.random_cells(300, 300, n_attr=2, rng_seed=43)
+        ev = cf.volume_of_radius(cf.radius_edges(8e-6, 14e-6, 1025))
     g = GpuRun(B, st, sink=False)
     g.step(5)
     xi, v, at = g.state()
-    ev = cf.volume_of_radius(cf.radius_edges(1e-6, 5e-3, 40))
     gm = g.sim.moments(ev)
     om = orc.moments(ocfg(orc, st), xi, v, np.ascontiguousarray(at), st.cell_off, ev)
     assert np.array_equal(gm["m0"], om["m0"])
@@ -603,6 +631,13 @@ def test_invalid_inputs(B):
     with pytest.raises(B.SdmError) as e:
         B.sdm_init(cfg, xi, v, None, off, small)
     assert e.value.status == B.SDM_ENOMEM
+    sim = B.Sim(st)  # more spectrum bins than sdm_moments takes
+    edges = torch.linspace(1e-18, 1e-12, 1026, dtype=torch.float64, device="cuda")
+    spec = torch.empty((st.n_cells, 1025), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.SdmError) as e:
+        B.sdm_moments(sim.handle, vol_edges=edges, spectrum=spec)
+    assert e.value.status == B.SDM_EINVAL
+    sim.close()
 
 
 def test_empty_and_tiny(B, orc):
