@@ -173,6 +173,40 @@ sdm_status sdm_coalescence_step(sdm_sim* s, int32_t n_steps, void* stream);
 sdm_status sdm_moments(sdm_sim* s, int64_t* m0, double* m12, double* attr_sums,
                        const double* vol_edges, int32_t n_bins, double* spectrum, void* stream);
 
+/*
+ * Diffusional growth (condensation / evaporation).  The paper lists
+ * condensational growth among the dynamics beside coalescence ("API in
+ * brief") and pairs it with ambient thermodynamics in its parcel examples
+ * ("Adiabatic parcel examples": activation of aerosol by supersaturation,
+ * hygroscopicity), without fixing the physics; the readings are:
+ * kappa-Koehler equilibrium saturation (Petters & Kreidenweis 2007), the
+ * Maxwell-Mason growth law r dr/dt = (S - S_eq) / (F_k + F_d) (Rogers & Yau
+ * 1989) with Bolton's saturation pressure and Pruppacher & Klett's
+ * diffusivity, and one implicit Euler step in r^2 solved by bracketed
+ * Newton iterations; the ambient state of each cell is held over the step.
+ * A super-droplet's dry volume and kappa x dry volume are two of its
+ * extensive attributes (summed on coalescence).  Only live wet volumes v
+ * change; the condensed mass of a cell follows from sdm_moments (M1) before
+ * and after.
+ */
+typedef struct {
+  double dt_s;             /* time step [s], > 0 */
+  int32_t dry_volume_attr; /* attribute holding the dry volume [m^3] */
+  int32_t kappa_attr;      /* attribute holding kappa x dry volume [m^3] (another one) */
+  int32_t max_iter;        /* Newton iterations per super-droplet, at most 64 (0: 32) */
+  int32_t reserved;        /* must be 0 */
+} sdm_cond_config;
+
+/* One condensation step of every live super-droplet (enqueue only, except that
+ * right after a device-side sdm_rebind the host copy of the offsets is
+ * refreshed with a blocking copy).  temperature [K], pressure [Pa] and
+ * saturation (saturation ratio, e.g. 1.002 for 0.2 % supersaturation):
+ * device arrays of n_cells values each, read on `stream`.  SDM_EINVAL for a
+ * bad config (attribute indices outside 0..n_attr-1 or equal); SDM_EAGAIN
+ * as for a step when the simulation is busy on another stream. */
+sdm_status sdm_condensation_step(sdm_sim* s, const sdm_cond_config* cc, const double* temperature,
+                                 const double* pressure, const double* saturation, void* stream);
+
 /* Device status word (SDM_FLAG_* bits); synchronises `stream`. */
 sdm_status sdm_status_word(sdm_sim* s, uint32_t* flags, void* stream);
 /* Clear the status word and the statistics counters (enqueue). */

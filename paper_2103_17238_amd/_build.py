@@ -15,7 +15,8 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function"]
-SOURCES = ["sdm_kernels.hip", "sdm_displace.hip", "sdm_refresh.hip", "sdm_api.cpp"]
+SOURCES = ["sdm_kernels.hip", "sdm_displace.hip", "sdm_refresh.hip", "sdm_condense.hip",
+           "sdm_api.cpp"]
 
 
 def hipcc() -> str:

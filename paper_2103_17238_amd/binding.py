@@ -30,7 +30,7 @@ EXPORTED = [
     "sdm_autotune", "sdm_batch_workspace_bytes", "sdm_batch_create", "sdm_batch_step",
     "sdm_batch_free", "sdm_free", "sdm_strerror", "sdm_philox_fill", "sdm_kernel_values",
     "sdm_rebind", "sdm_displace_workspace_bytes", "sdm_displace", "sdm_displace_noalloc",
-    "sdm_displace_noalloc_max_cells",
+    "sdm_displace_noalloc_max_cells", "sdm_condensation_step",
 ]
 
 
@@ -132,6 +132,19 @@ _sig("sdm_displace_noalloc", _S, C.POINTER(sdm_displace_args), _P)
 _sig("sdm_displace_noalloc_max_cells", C.c_int64)
 
 
+class sdm_cond_config(C.Structure):
+    _fields_ = [
+        ("dt_s", C.c_double),
+        ("dry_volume_attr", C.c_int32),
+        ("kappa_attr", C.c_int32),
+        ("max_iter", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+_sig("sdm_condensation_step", _S, _H, C.POINTER(sdm_cond_config), _P, _P, _P, _P)
+
+
 class SdmError(RuntimeError):
     def __init__(self, call, status):
         super().__init__(f"{call} failed: {_lib.sdm_strerror(status).decode()} ({status})")
@@ -192,6 +205,13 @@ def sdm_init(cfg: sdm_config, xi, v, attrs, cell_off, workspace, stream=None):
 
 def sdm_coalescence_step(h, n_steps: int, stream=None):
     _check("sdm_coalescence_step", _lib.sdm_coalescence_step(h, int(n_steps), _stream(stream)))
+
+
+def sdm_condensation_step(h, cc: sdm_cond_config, temperature, pressure, saturation,
+                          stream=None):
+    _check("sdm_condensation_step",
+           _lib.sdm_condensation_step(h, C.byref(cc), _ptr(temperature), _ptr(pressure),
+                                      _ptr(saturation), _stream(stream)))
 
 
 def sdm_moments(h, m0=None, m12=None, attr_sums=None, vol_edges=None, spectrum=None,

@@ -817,6 +817,58 @@ sdm_status sdm_coalescence_step(sdm_sim* s, int32_t n_steps, void* stream) {
   return plan_step(s->plan, n_steps, reinterpret_cast<hipStream_t>(stream));
 }
 
+sdm_status sdm_condensation_step(sdm_sim* s, const sdm_cond_config* cc, const double* temperature,
+                                 const double* pressure, const double* saturation, void* stream) {
+  if (!s || !cc || !temperature || !pressure || !saturation) return SDM_EINVAL;
+  const int A = s->cfg.n_attr;
+  if (!(cc->dt_s > 0.0) || !std::isfinite(cc->dt_s) || cc->reserved != 0 ||
+      cc->dry_volume_attr < 0 || cc->dry_volume_attr >= A || cc->kappa_attr < 0 ||
+      cc->kappa_attr >= A || cc->dry_volume_attr == cc->kappa_attr || cc->max_iter < 0 ||
+      cc->max_iter > 64)
+    return SDM_EINVAL;
+  if (s->broken) return SDM_ESTATE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (s->last && s->last->st != st) {  // busy on another stream: enqueue nothing
+    const hipError_t q = hipEventQuery(s->last->ev);
+    if (q == hipErrorNotReady) {
+      (void)hipGetLastError();
+      return SDM_EAGAIN;
+    }
+    if (q != hipSuccess) {
+      (void)hipGetLastError();
+      return SDM_EDEVICE;
+    }
+  }
+  if (!fresh_offsets(s)) return SDM_EDEVICE;
+  int64_t max_cell = 0;
+  for (int c = 0; c < s->cfg.n_cells; ++c)
+    max_cell = std::max<int64_t>(max_cell, s->off[c + 1] - s->off[c]);
+  if (max_cell == 0) return SDM_OK;
+  const int64_t ns = s->cfg.n_slots;
+  if (sdm::launch_condense(s->xi, s->v, s->attrs + (int64_t)cc->dry_volume_attr * ns,
+                           s->attrs + (int64_t)cc->kappa_attr * ns, s->cell_off, s->cfg.n_cells,
+                           max_cell, temperature, pressure, saturation, cc->dt_s,
+                           cc->max_iter > 0 ? cc->max_iter : 32, st) != hipSuccess)
+    return SDM_EDEVICE;
+  // the simulation is busy on `st` until this event (its plan's token)
+  Plan* p = s->plan;
+  if (!p->busy) {
+    p->busy = std::make_shared<Busy>();
+    if (hipEventCreateWithFlags(&p->busy->ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      p->busy.reset();
+      return SDM_EDEVICE;
+    }
+  }
+  if (hipEventRecord(p->busy->ev, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return SDM_EDEVICE;
+  }
+  p->busy->st = st;
+  s->last = p->busy;
+  return SDM_OK;
+}
+
 sdm_status sdm_moments(sdm_sim* s, int64_t* m0, double* m12, double* attr_sums,
                        const double* vol_edges, int32_t n_bins, double* spectrum, void* stream) {
   if (!s || n_bins < 0) return SDM_EINVAL;

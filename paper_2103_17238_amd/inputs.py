@@ -206,6 +206,66 @@ def grid_256x256(seed: int = 0) -> State:
 
 
 # ---------------------------------------------------------------------------
+# Condensation workloads: the first two extensive attributes are the dry
+# volume and kappa x dry volume; the ambient state is given per cell
+# ---------------------------------------------------------------------------
+
+def _aerosol(rng, n, wet_v, haze_fraction=1 / 3):
+    """Dry volumes (lognormal dry radius, median 40 nm, sigma_g 1.6), kappa
+    (two modes, 0.6 and 0.1, half each) and wet volumes: a haze fraction at
+    1.1-3 times the dry radius, the rest keep wet_v (at least the dry volume)."""
+    rd = 40e-9 * 1.6 ** rng.normal(0.0, 1.0, size=n)
+    vd = sphere_volume(rd)
+    kappa = np.where(rng.random(n) < 0.5, 0.6, 0.1)
+    haze = rng.random(n) < haze_fraction
+    v = np.where(haze, sphere_volume(rd * rng.uniform(1.1, 3.0, size=n)), np.maximum(wet_v, vd))
+    return v, np.stack([vd, kappa * vd])
+
+
+def ambient(n_cells: int, seed: int = 6, s_lo: float = 0.995, s_hi: float = 1.005):
+    """Per-cell temperature U(275, 295) K, pressure U(70, 100) kPa and
+    saturation ratio U(s_lo, s_hi) (default_rng(seed))."""
+    rng = np.random.default_rng(seed)
+    return {"T": rng.uniform(275.0, 295.0, n_cells), "p": rng.uniform(70e3, 100e3, n_cells),
+            "S": rng.uniform(s_lo, s_hi, n_cells)}
+
+
+def aerosol_cells(n_cells: int, max_sd: int, n_attr: int = 2, rng_seed: int = 0,
+                  dead_fraction: float = 0.1) -> State:
+    """Uneven cells (empty and one-SD cells included, sizes up to max_sd) of
+    aerosol and cloud droplets for condensation: attributes 0 and 1 are the
+    dry volume and kappa x dry volume, further ones lognormal."""
+    rng = np.random.default_rng(rng_seed)
+    counts = rng.integers(0, max_sd + 1, size=n_cells)
+    if n_cells >= 3:
+        counts[0], counts[1], counts[2] = 0, 1, max_sd
+    cell_off = np.zeros(n_cells + 1, dtype=np.int64)
+    np.cumsum(counts, out=cell_off[1:])
+    n = int(cell_off[-1])
+    xi = rng.integers(1, 10 ** 9, size=n, dtype=np.int64)
+    xi[rng.random(n) < dead_fraction] = 0
+    wet = sphere_volume(10e-6 * 1.6 ** rng.normal(0.0, 1.0, size=n))
+    v, a2 = _aerosol(rng, n, wet)
+    attrs = np.concatenate([a2, _attr_values(rng, n_attr - 2, n)]) if n_attr > 2 else a2
+    return State(xi, v, attrs, cell_off, dt=1.0, dv=1e6, kernel=GEOMETRIC, b=1500.0,
+                 seed=rng_seed, meta={"workload": "aerosol_cells"})
+
+
+def condensation_grid(nx: int = 256, ny: int = 256, seed: int = 0) -> State:
+    """The 256 x 256 grid layout (Poisson(256) SDs per cell, cloud mode of
+    median radius 10 um) with an aerosol population (default_rng(7)): dry
+    volume and kappa x dry volume as attributes 0 and 1, a third of the SDs
+    haze particles, and 4 further lognormal attributes (6 in all)."""
+    st = grid(nx, ny, 256, n_attr=0, dv=2e6, kernel=GEOMETRIC, seed=seed)
+    rng = np.random.default_rng(7)
+    v, a2 = _aerosol(rng, st.n_slots, st.v)
+    st.v = v
+    st.attrs = np.concatenate([a2, _attr_values(np.random.default_rng(1), 4, st.n_slots)])
+    st.meta = {"workload": "condensation_grid", "nx": nx, "ny": ny}
+    return st
+
+
+# ---------------------------------------------------------------------------
 # Serving workload: a stream of box requests
 # ---------------------------------------------------------------------------
 

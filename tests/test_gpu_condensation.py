@@ -1,0 +1,170 @@
+"""GPU parity of the condensation step (sdm_condensation_step through the C
+ABI) against the CPU oracle (oracle/condensation.py).
+
+Tolerance, from the arithmetic: the device and the oracle run the same
+sequence of fp64 operations, but exp, pow, cbrt and sqrt of the device
+library and of numpy may differ by an ulp or two.  The implicit step solves
+x1 = x0 + c (S - S_eq(x1)); an error of a few ulps in c or S_eq moves x1 by
+about c S times those ulps, divided by the slope g' = 1 + c dS_eq/dx of the
+implicit equation at the root.  Relative to x1 that is (c S / (x1 g')) times
+a few ulps: tiny for cloud droplets (c S / x1 of order 1), up to 1e5 for
+haze particles, whose step is far larger than themselves, and larger again
+just past the critical radius, where g' drops below 1.  The bar per wet
+volume v (v ~ x^1.5) is
+    |v_gpu - v_oracle| <= v (1e-12 + 1.5 x 32 eps c S / (x1 max(g', 1e-3))),
+eps = 2^-53, with g' evaluated by the oracle at its root; at most 1e-6 of
+the super-droplets may lie beyond it (the marginal cases where the iteration
+can take another of several roots, see the oracle).  Every step is compared
+from the same input state (the device's
+previous one), so differences do not compound."""
+import numpy as np
+import pytest
+
+from oracle import condensation as cd
+from paper_2103_17238_amd import inputs as I
+
+from sdm_testutil import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_17238_amd import binding
+
+    return binding
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _cond(B, dt, max_iter=0):
+    return B.sdm_cond_config(dt, 0, 1, max_iter, 0)
+
+
+EPS = 2.0 ** -53
+
+
+def _compare(v_gpu, v_orc, label, xi, attrs, cell_off, amb, dt):
+    """Every live wet volume against the bar above (g' from the oracle)."""
+    cell = np.repeat(np.arange(len(cell_off) - 1), np.diff(cell_off))
+    T, p, S = amb["T"][cell], amb["p"][cell], amb["S"][cell]
+    fk, fd = cd.growth_terms(T, p)
+    c = 2.0 * dt / (fk + fd)
+    vd = attrs[0]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        kappa = np.where(vd > 0, attrs[1] / vd, 0.0)
+    x1 = np.cbrt(np.abs(v_orc) / cd.FOUR_PI_3) ** 2
+    gp = 1.0 + c * cd.s_eq_dx(x1, vd / cd.FOUR_PI_3, kappa, cd.kelvin_a(T))
+    live = xi > 0
+    rel = (np.abs(v_gpu - v_orc) / np.abs(v_orc).clip(1e-300))[live]
+    bar = (1e-12 + 1.5 * 32 * EPS * c * S / (x1.clip(1e-300) * np.maximum(gp, 1e-3)))[live]
+    bad = int((rel > bar).sum())
+    say(f"  {label}: max rel {rel.max():.2e}, max rel / bar {(rel / bar).max():.2f}, "
+        f"beyond the bar: {bad} of {rel.size}")
+    assert bad <= 1e-6 * rel.size, (label, bad)
+    return bad
+
+
+@pytest.mark.parametrize("dt,s_lo,s_hi", [(1.0, 0.995, 1.005), (0.1, 0.9, 1.01), (5.0, 1.0, 1.01)])
+def test_uneven_cells_against_oracle(B, dt, s_lo, s_hi):
+    """Uneven cells (empty, one-SD, up to 3000 slots: several 1024-slot parts
+    per cell), dead slots, haze and cloud droplets, two kappa modes, one
+    extra attribute; five steps, each compared with the oracle's step from
+    the same input (the device's previous state: teacher forcing, so that
+    last-bit differences do not compound over the steps)."""
+    st = I.aerosol_cells(40, 3000, n_attr=3, rng_seed=int(dt * 10) + 1)
+    amb = I.ambient(st.n_cells, seed=9, s_lo=s_lo, s_hi=s_hi)
+    sim = B.Sim(st)
+    T, p, S = _dev(amb["T"]), _dev(amb["p"]), _dev(amb["S"])
+    v = st.v.copy()
+    for k in range(5):
+        B.sdm_condensation_step(sim.handle, _cond(B, dt), T, p, S)
+        cd.step(st.xi, v, st.attrs, st.cell_off, amb["T"], amb["p"], amb["S"], dt, 0, 1)
+        xi_g, v_g, a_g = sim.state()
+        assert np.array_equal(xi_g, st.xi) and np.array_equal(a_g, st.attrs)
+        _compare(v_g, v, f"dt={dt} step {k}", st.xi, st.attrs, st.cell_off, amb, dt)
+        dead = st.xi == 0
+        assert np.array_equal(v_g[dead], st.v[dead])
+        v[:] = v_g
+    sim.close()
+
+
+def test_condensation_then_coalescence(B, orc):
+    """Condensation and coalescence alternating on the same state (the dry
+    volume and kappa x dry volume summed on coalescence): three rounds, the
+    multiplicities bit-exact and the volumes and attributes within the bar."""
+    from sdm_testutil import ocfg
+
+    st = I.aerosol_cells(12, 600, n_attr=2, rng_seed=21)
+    st.b *= 300.0
+    st.kernel = I.GOLOVIN
+    amb = I.ambient(st.n_cells, seed=10, s_lo=0.99, s_hi=1.01)
+    sim = B.Sim(st)
+    T, p, S = _dev(amb["T"]), _dev(amb["p"]), _dev(amb["S"])
+    o = st.copy()
+    cfg = ocfg(orc, o)
+    for k in range(3):
+        B.sdm_condensation_step(sim.handle, _cond(B, 1.0), T, p, S)
+        _, v_g, _ = sim.state()
+        cd.step(o.xi, o.v, o.attrs, o.cell_off, amb["T"], amb["p"], amb["S"], 1.0, 0, 1)
+        _compare(v_g, o.v, f"condensed {k}", o.xi, o.attrs, o.cell_off, amb, 1.0)
+        # the coalescence step continues from the device's condensed volumes
+        # (teacher forcing: a last-bit difference cannot flip a gamma)
+        o.v[:] = v_g
+        sim.step(1)
+        orc.step(cfg, o.xi, o.v, o.attrs, o.cell_off, k)
+        xi_g, v_g, a_g = sim.state()
+        assert np.array_equal(xi_g, o.xi), k
+        assert np.array_equal(v_g, o.v) and np.array_equal(a_g, o.attrs), k
+    sim.close()
+
+
+def test_condensation_grid_sampled(B):
+    """The 256 x 256 condensation grid (16.8 M slots, 6 attributes) in the
+    launch the benchmark times: one step on the GPU, 2000 sampled cells
+    against the oracle."""
+    st = I.condensation_grid()
+    amb = I.ambient(st.n_cells, seed=6)
+    sim = B.Sim(st)
+    T, p, S = _dev(amb["T"]), _dev(amb["p"]), _dev(amb["S"])
+    B.sdm_condensation_step(sim.handle, _cond(B, 1.0), T, p, S)
+    _, v_g, _ = sim.state()
+    sim.close()
+    cells = np.random.default_rng(12).choice(st.n_cells, 2000, replace=False)
+    sl = np.concatenate([np.arange(st.cell_off[c], st.cell_off[c + 1]) for c in cells])
+    sub_off = np.concatenate([[0], np.cumsum(np.diff(st.cell_off)[cells])]).astype(np.int64)
+    v = st.v[sl].copy()
+    sub_amb = {k: amb[k][cells] for k in ("T", "p", "S")}
+    cd.step(st.xi[sl], v, st.attrs[:, sl], sub_off, sub_amb["T"], sub_amb["p"], sub_amb["S"],
+            1.0, 0, 1)
+    _compare(v_g[sl], v, "grid256 sample", st.xi[sl], st.attrs[:, sl], sub_off, sub_amb, 1.0)
+
+
+def test_condensation_invalid_arguments(B):
+    import torch
+
+    st = I.aerosol_cells(4, 50, n_attr=2, rng_seed=3)
+    sim = B.Sim(st)
+    T = _dev(np.full(4, 280.0))
+    p = _dev(np.full(4, 9e4))
+    S = _dev(np.full(4, 1.001))
+    for cc in [B.sdm_cond_config(0.0, 0, 1, 0, 0), B.sdm_cond_config(1.0, 0, 0, 0, 0),
+               B.sdm_cond_config(1.0, 0, 2, 0, 0), B.sdm_cond_config(1.0, -1, 1, 0, 0),
+               B.sdm_cond_config(1.0, 0, 1, 65, 0), B.sdm_cond_config(1.0, 0, 1, 0, 1)]:
+        with pytest.raises(B.SdmError) as e:
+            B.sdm_condensation_step(sim.handle, cc, T, p, S)
+        assert e.value.status == B.SDM_EINVAL
+    with pytest.raises(B.SdmError):
+        B.sdm_condensation_step(sim.handle, _cond(B, 1.0), None, p, S)
+    xi0, v0, _ = sim.state()
+    assert np.array_equal(v0, st.v)  # nothing was enqueued
+    torch.cuda.synchronize()
+    sim.close()
