@@ -88,6 +88,23 @@ def displace_traffic_from_profiles():
     return (d["fetch_kib_per_step"] + d["write_kib_per_step"]) * 1024.0
 
 
+def condense_source_sha():
+    with open(os.path.join(ROOT, "paper_2103_17238_amd", "csrc", "sdm_condense.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def condense_traffic_from_profiles():
+    """HBM bytes per condensation step from the committed rocprofv3 --pmc
+    summary, if it was taken on the current source; else None."""
+    try:
+        d = json.load(open(os.path.join(PROFILES, "k_condense_grid256_pmc.json")))
+    except (OSError, ValueError):
+        return None
+    if d.get("condense_source_sha") != condense_source_sha():
+        return None
+    return (d["fetch_kib_per_step"] + d["write_kib_per_step"]) * 1024.0
+
+
 CLASS_CAPS = (64, 128, 256, 384, 512)
 
 
@@ -702,7 +719,7 @@ def condense_bench(args):
                    "parallelism": "1 GPU, one block per cell and 1024-slot part"},
         "roofline": {"bound": "hbm", "kernel": "k_condense", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes_per_launch": alg,
+                     "traffic": condense_traffic_from_profiles(), "alg_bytes_per_launch": alg,
                      "avg_launch_ms": total_s / K * 1e3, "copy_gbs": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs},
         "wall_s": wall,
