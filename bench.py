@@ -93,6 +93,21 @@ def condense_source_sha():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
+def condense_valu_from_profiles(step_s):
+    """VALU issue of the condensation step from the committed SQ counters of
+    the same source, over the measured step time; None if they do not match."""
+    try:
+        d = json.load(open(os.path.join(PROFILES, "k_condense_grid256_pmc.json")))
+    except (OSError, ValueError):
+        return None
+    if d.get("condense_source_sha") != condense_source_sha() or "sq_insts_valu_per_step" not in d:
+        return None
+    achieved = d["sq_insts_valu_per_step"] / step_s
+    return {"bound": "valu-issue", "unit": "wave64 VALU instructions/s",
+            "insts_per_step": d["sq_insts_valu_per_step"], "achieved": achieved,
+            "peak": VALU_PEAK_WAVE_INSTS, "frac": achieved / VALU_PEAK_WAVE_INSTS}
+
+
 def condense_traffic_from_profiles():
     """HBM bytes per condensation step from the committed rocprofv3 --pmc
     summary, if it was taken on the current source; else None."""
@@ -722,6 +737,7 @@ def condense_bench(args):
                      "traffic": condense_traffic_from_profiles(), "alg_bytes_per_launch": alg,
                      "avg_launch_ms": total_s / K * 1e3, "copy_gbs": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs},
+        "valu": condense_valu_from_profiles(total_s / K),
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:

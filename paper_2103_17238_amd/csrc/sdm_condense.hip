@@ -20,10 +20,12 @@
 // the bracket closes in on the iterate by the sign of g; the iteration stops
 // when a step is at most 1e-14 of x, or after max_iter iterations.
 //
-// Data: each thread takes slots j = part 1024 + r 256 + tid (r < 4) of one
-// cell (blockIdx.x the cell, blockIdx.y the 1024-slot part), so the reads of
-// xi, v and the two attributes are coalesced; the cell's ambient values are
-// read once per block.  Bound: HBM for the state (40 B per live slot:
+// Data: each thread takes slot j = part 256 + tid of one cell (blockIdx.x
+// the cell, blockIdx.y the 256-slot part), so the reads of xi, v and the two
+// attributes are coalesced; the cell's ambient terms are computed once per
+// block.  One slot per thread keeps the registers low and the occupancy high:
+// the Newton iteration is a chain of dependent fp64 operations, and it is the
+// other wavefronts of the SIMD that hide its latency.  Bound: HBM for the state (40 B per live slot:
 // xi, v, dry volume and kappa dry volume read, v written), fp64 ALU for the
 // exp / sqrt / cbrt of the Newton iterations.
 #include "sdm_internal.hpp"
@@ -40,7 +42,7 @@ constexpr double kKair = 2.4e-2;   // W/(m K)
 constexpr double kD0 = 2.11e-5;    // m^2/s at 273.15 K, 101325 Pa
 constexpr double kCondTol = 1e-14;
 constexpr int kCondThreads = 256;
-constexpr int kCondPart = 4 * kCondThreads;  // slots per block
+constexpr int kCondPart = kCondThreads;  // slots per block (one per thread)
 
 // equilibrium saturation ratio and its derivative in x = r^2 (0 at or below
 // the dry size)
@@ -70,58 +72,55 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(
   const int64_t n = cell_off[c + 1] - o0;
   const int64_t base = (int64_t)blockIdx.y * kCondPart;
   if (base >= n) return;
-  // the cell's ambient terms
-  const double T = temp[c], p = pres[c], S = sat[c];
-  const double es = 611.2 * exp(17.67 * (T - 273.15) / (T - 29.65));
-  const double D = kD0 * pow(T / 273.15, 1.94) * (101325.0 / p);
-  const double fk = (kLv / (kRv * T) - 1.0) * kLv * kRhoW / (kKair * T);
-  const double fd = kRhoW * kRv * T / (D * es);
-  const double cc = 2.0 * dt / (fk + fd);
-  const double a = 2.0 * kSigma / (kRhoW * kRv * T);
-  // every slot's state first (coalesced), then the solves
-  long long xr[4];
-  double vr[4], vd[4], kv[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t j = base + r * kCondThreads + threadIdx.x;
-    xr[r] = 0;
-    vr[r] = vd[r] = kv[r] = 0.0;
-    if (j < n) xr[r] = xi[o0 + j];
-    if (xr[r] > 0) {
-      vr[r] = v[o0 + j];
-      vd[r] = vdry[o0 + j];
-      kv[r] = kvdry[o0 + j];
-    }
+  const int64_t j = base + threadIdx.x;
+  long long x_ = 0;
+  double v_ = 0.0, vd = 0.0, kv = 0.0;
+  if (j < n) x_ = xi[o0 + j];
+  if (x_ > 0) {  // the state first (coalesced), then the solve
+    v_ = v[o0 + j];
+    vd = vdry[o0 + j];
+    kv = kvdry[o0 + j];
   }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    if (xr[r] <= 0) continue;
-    const int64_t j = base + r * kCondThreads + threadIdx.x;
-    const double kappa = vd[r] > 0.0 ? kv[r] / vd[r] : 0.0;
-    const double rd3 = vd[r] / kFourPi3;
-    const double rd = cbrt(rd3);
-    const double xd = rd * rd;
-    const double r0 = cbrt(fmax(vr[r], vd[r]) / kFourPi3);
-    const double x0 = fmax(r0 * r0, xd);
-    double lo = xd, hi = fmax(xd, x0 + cc * S);
-    double x = fmin(fmax(x0, lo), hi);
-    for (int it = 0; it < max_iter; ++it) {
-      double se, dse;
-      s_eq_and_slope(x, rd3, kappa, a, se, dse);
-      const double g = x - x0 - cc * (S - se);
-      const double gp = 1.0 + cc * dse;
-      if (g == 0.0) break;
-      if (g < 0.0) lo = x;
-      else if (g > 0.0) hi = x;
-      double xn = x - g / gp;
-      if (!(gp > 0.0) || !(xn >= lo) || !(xn <= hi)) xn = 0.5 * (lo + hi);
-      const bool done = fabs(xn - x) <= kCondTol * xn;
-      x = xn;
-      if (done) break;
-    }
-    const double r1 = sqrt(x);
-    v[o0 + j] = kFourPi3 * (x * r1);
+  // the cell's ambient terms, by one thread for the block (a pow and an exp
+  // would otherwise cost each wavefront as much as its droplets)
+  __shared__ double amb[3];
+  if (threadIdx.x == 0) {
+    const double T = temp[c], p = pres[c];
+    const double es = 611.2 * exp(17.67 * (T - 273.15) / (T - 29.65));
+    const double D = kD0 * pow(T / 273.15, 1.94) * (101325.0 / p);
+    const double fk = (kLv / (kRv * T) - 1.0) * kLv * kRhoW / (kKair * T);
+    const double fd = kRhoW * kRv * T / (D * es);
+    amb[0] = 2.0 * dt / (fk + fd);
+    amb[1] = 2.0 * kSigma / (kRhoW * kRv * T);
+    amb[2] = sat[c];
   }
+  __syncthreads();
+  if (x_ <= 0) return;
+  const double cc = amb[0], a = amb[1], S = amb[2];
+  const double kappa = vd > 0.0 ? kv / vd : 0.0;
+  const double rd3 = vd / kFourPi3;
+  const double rd = cbrt(rd3);
+  const double xd = rd * rd;
+  const double r0 = cbrt(fmax(v_, vd) / kFourPi3);
+  const double x0 = fmax(r0 * r0, xd);
+  double lo = xd, hi = fmax(xd, x0 + cc * S);
+  double x = fmin(fmax(x0, lo), hi);
+  for (int it = 0; it < max_iter; ++it) {
+    double se, dse;
+    s_eq_and_slope(x, rd3, kappa, a, se, dse);
+    const double g = x - x0 - cc * (S - se);
+    const double gp = 1.0 + cc * dse;
+    if (g == 0.0) break;
+    if (g < 0.0) lo = x;
+    else if (g > 0.0) hi = x;
+    double xn = x - g / gp;
+    if (!(gp > 0.0) || !(xn >= lo) || !(xn <= hi)) xn = 0.5 * (lo + hi);
+    const bool done = fabs(xn - x) <= kCondTol * xn;
+    x = xn;
+    if (done) break;
+  }
+  const double r1 = sqrt(x);
+  v[o0 + j] = kFourPi3 * (x * r1);
 }
 
 hipError_t launch_condense(const int64_t* xi, double* v, const double* vdry, const double* kvdry,

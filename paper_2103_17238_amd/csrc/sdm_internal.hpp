@@ -183,7 +183,7 @@ struct SideStream {
 hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
                        int waves_per_cell, hipStream_t st, const SideStream& side);
 // Diffusional growth of every live super-droplet of one simulation
-// (sdm_condense.hip): one block per (cell, 1024-slot part).
+// (sdm_condense.hip): one block per (cell, 256-slot part).
 hipError_t launch_condense(const int64_t* xi, double* v, const double* vdry, const double* kvdry,
                            const int64_t* cell_off, int n_cells, int64_t max_cell,
                            const double* temp, const double* pres, const double* sat, double dt,

@@ -75,7 +75,7 @@ def _compare(v_gpu, v_orc, label, xi, attrs, cell_off, amb, dt):
 
 @pytest.mark.parametrize("dt,s_lo,s_hi", [(1.0, 0.995, 1.005), (0.1, 0.9, 1.01), (5.0, 1.0, 1.01)])
 def test_uneven_cells_against_oracle(B, dt, s_lo, s_hi):
-    """Uneven cells (empty, one-SD, up to 3000 slots: several 1024-slot parts
+    """Uneven cells (empty, one-SD, up to 3000 slots: several 256-slot parts
     per cell), dead slots, haze and cloud droplets, two kappa modes, one
     extra attribute; five steps, each compared with the oracle's step from
     the same input (the device's previous state: teacher forcing, so that
