@@ -410,14 +410,55 @@ __device__ __forceinline__ uint16_t* perm_of(CellLds<CAP>& L) {
   return reinterpret_cast<uint16_t*>(L.tmp);
 }
 
+// Slots a thread owns in the sort and pair phases of a workgroup-per-cell
+// class: 4, the words of one Philox call, or 6 for one-wave 384-slot cells.
+// The work a wave issues per phase is (rounds x slots per thread): 2 x 4 = 8
+// slot-works for a 384-slot capacity, 1 x 6 = 6 with six (still two Philox
+// calls per thread: six consecutive slots from an even start lie in two
+// groups of 4).  For 512 slots 2 x 4 = 1 x 8, so four stay.
+template <int CAP, int W>
+constexpr int slots_per_thread() {
+  return (CAP == 384 && W == 1) ? 6 : 4;
+}
+template <int CAP, int W>
+constexpr int sort_rounds() {
+  return (CAP + slots_per_thread<CAP, W>() * 64 * W - 1) / (slots_per_thread<CAP, W>() * 64 * W);
+}
+
+// the 32-bit keys of slots j0 .. j0 + SPT - 1 (j0 a multiple of SPT): word
+// j mod 4 of Philox((j / 4, c, s, 2u))
+template <int SPT>
+__device__ __forceinline__ void slot_keys(int j0, int c, uint32_t s, uint32_t u, uint32_t k0,
+                                          uint32_t k1, uint32_t (&kr)[SPT]) {
+  const uint32_t ga = (uint32_t)j0 >> 2;
+  const uint4 wa = philox(make_uint4(ga, (uint32_t)c, s, 2u * u), k0, k1);
+  if constexpr (SPT == 4) {
+    kr[0] = wa.x;
+    kr[1] = wa.y;
+    kr[2] = wa.z;
+    kr[3] = wa.w;
+  } else {
+    static_assert(SPT == 6, "4 or 6 slots per thread");
+    const uint4 wb = philox(make_uint4(ga + 1u, (uint32_t)c, s, 2u * u), k0, k1);
+    const bool odd = (j0 & 3) != 0;  // j0 mod 4 is 0 or 2
+    kr[0] = odd ? wa.z : wa.x;
+    kr[1] = odd ? wa.w : wa.y;
+    kr[2] = odd ? wb.x : wa.z;
+    kr[3] = odd ? wb.y : wa.w;
+    kr[4] = odd ? wb.z : wb.x;
+    kr[5] = odd ? wb.w : wb.y;
+  }
+}
+
 // keys, bucket count, scan, scatter, rank: permutation of the nlive live slots
 template <int CAP, int W>
 __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int tid, int lane,
                                           int wv, int c, uint32_t s, uint32_t u, uint32_t k0,
                                           uint32_t k1) {
   constexpr int T = 64 * W;
-  constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);  // 4-slot groups per thread
-  const int nbits = 32 - __clz(n - 1);              // n >= 2
+  constexpr int SPT = slots_per_thread<CAP, W>();
+  constexpr int I4 = sort_rounds<CAP, W>();  // rounds of SPT slots per thread
+  const int nbits = 32 - __clz(n - 1);        // n >= 2
   const int nb = 1 << nbits;
   const int sh = 32 - nbits;
   for (int i = 4 * tid; i < nb + 4; i += 4 * T)  // counters 0..nb, 16 bytes at a time
@@ -425,30 +466,34 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
   team_sync<W>();
 
   // keys of live slots (registers) and their place in their bucket (atomics)
-  uint32_t me[I4][4], pos[I4][4], bk[I4][4];
+  uint32_t me[I4][SPT], pos[I4][SPT], bk[I4][SPT];
   uint32_t live[I4];
 #pragma unroll
   for (int i = 0; i < I4; ++i) {
-    const int g = T * i + tid;
+    const int j0 = SPT * (T * i + tid);
     live[i] = 0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < SPT; ++e) {
       me[i][e] = 0;
       pos[i][e] = 0;
       bk[i][e] = 0;
     }
-    if (4 * g < n) {
-      const uint4 w = philox(make_uint4((uint32_t)g, (uint32_t)c, s, 2u * u), k0, k1);
-      const uint32_t kr[4] = {w.x, w.y, w.z, w.w};
-      const double2 x01 = *reinterpret_cast<const double2*>(&L.xd[4 * g]);
-      const double2 x23 = *reinterpret_cast<const double2*>(&L.xd[4 * g + 2]);
-      const double xv[4] = {x01.x, x01.y, x23.x, x23.y};
+    if (j0 < n) {
+      uint32_t kr[SPT];
+      slot_keys<SPT>(j0, c, s, u, k0, k1, kr);
+      double xv[SPT];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const bool lv = 4 * g + e < n && xv[e] > 0.0;
+      for (int e = 0; e < SPT; e += 2) {  // j0 is even: 16-byte LDS reads
+        const double2 x2 = *reinterpret_cast<const double2*>(&L.xd[j0 + e]);
+        xv[e] = x2.x;
+        xv[e + 1] = x2.y;
+      }
+#pragma unroll
+      for (int e = 0; e < SPT; ++e) {
+        const bool lv = j0 + e < n && xv[e] > 0.0;
         live[i] |= lv ? 1u << e : 0u;
         bk[i][e] = kr[e] >> sh;
-        me[i][e] = (kr[e] << nbits) | (uint32_t)(4 * g + e);
+        me[i][e] = (kr[e] << nbits) | (uint32_t)(j0 + e);
         if (lv) pos[i][e] = atomicAdd(&L.cnt[bk[i][e]], 1u);
       }
     }
@@ -470,11 +515,11 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
   }
   team_sync<W>();
   // scatter: every bucket range is read before the first store
-  uint32_t st[I4][4], len[I4][4];
+  uint32_t st[I4][SPT], len[I4][SPT];
 #pragma unroll
   for (int i = 0; i < I4; ++i)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < SPT; ++e) {
       const uint32_t b = ((live[i] >> e) & 1) ? bk[i][e] : 0u;  // counters 0..nb are valid
       st[i][e] = L.cnt[b];
       len[i][e] = L.cnt[b + 1];
@@ -483,7 +528,7 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
 #pragma unroll
   for (int i = 0; i < I4; ++i)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < SPT; ++e) {
       const bool lv = (live[i] >> e) & 1;
       len[i][e] = lv ? len[i][e] - st[i][e] : 0u;
       st[i][e] = lv ? st[i][e] : 0u;
@@ -493,21 +538,22 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
   team_sync<W>();
   // exact rank inside the bucket: each round reads one entry of every
   // bucket of the thread (clamped into the array; masked beyond the bucket)
-  uint32_t rk[I4][4];
+  uint32_t rk[I4][SPT];
 #pragma unroll
   for (int i = 0; i < I4; ++i)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) rk[i][e] = st[i][e];
+    for (int e = 0; e < SPT; ++e) rk[i][e] = st[i][e];
   for (int k = 0; k < maxlen; ++k) {
-    uint32_t x[I4][4];
+    uint32_t x[I4][SPT];
 #pragma unroll
     for (int i = 0; i < I4; ++i)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) x[i][e] = L.tmp[min(st[i][e] + (uint32_t)k, (uint32_t)CAP - 1u)];
+      for (int e = 0; e < SPT; ++e)
+        x[i][e] = L.tmp[min(st[i][e] + (uint32_t)k, (uint32_t)CAP - 1u)];
 #pragma unroll
     for (int i = 0; i < I4; ++i)
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < SPT; ++e)
         rk[i][e] += ((uint32_t)k < len[i][e] && x[i][e] < me[i][e]) ? 1u : 0u;
   }
   team_sync<W>();
@@ -515,8 +561,8 @@ __device__ __forceinline__ void team_sort(CellLds<CAP>& L, int n, int nlive, int
 #pragma unroll
   for (int i = 0; i < I4; ++i)
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if ((live[i] >> e) & 1) perm[rk[i][e]] = (uint16_t)(4 * (T * i + tid) + e);
+    for (int e = 0; e < SPT; ++e)
+      if ((live[i] >> e) & 1) perm[rk[i][e]] = (uint16_t)(SPT * (T * i + tid) + e);
   if (tid == 0) L.nlist = 0;
   team_sync<W>();
 }
@@ -526,14 +572,41 @@ enum PassMode { kPassPlain = 0, kPassPmax = 1, kPassAdapt = 2, kPassPlainLds = 3
 // Registers a thread carries between the two passes of an adaptive substep:
 // the slots of its pairs (from the permutation) and their pre-products
 // (max xi K) S.
-template <int I4>
+template <int I4, int SPT>
 struct PairRegs {
-  uint2 o4[I4];
-  double pre[I4][2];
+  uint32_t o[I4][SPT / 2];  // permutation entries, two 16-bit slots per word
+  double pre[I4][SPT / 2];
 };
 
-// Candidate pairs of one (sub)step; thread h takes sorted positions 4h..4h+3,
-// i.e. pairs 2h and 2h+1, which share one Philox call.  kPassPlain updates
+// The uniforms of pairs NP h .. NP h + NP - 1 (NP = SPT / 2): pair m takes
+// words 2 (m mod 2) and 2 (m mod 2) + 1 of Philox((m / 2, c, s, 2u + 1)) as
+// the high and low halves; 4 slots per thread need one call, 6 need two.
+template <int SPT>
+__device__ __forceinline__ void pair_uniforms(int h, int c, uint32_t s, uint32_t u, uint32_t k0,
+                                              uint32_t k1, double (&phi)[SPT / 2]) {
+  if constexpr (SPT == 4) {
+    const uint4 w = philox(make_uint4((uint32_t)h, (uint32_t)c, s, 2u * u + 1u), k0, k1);
+    phi[0] = uniform53(w.x, w.y);
+    phi[1] = uniform53(w.z, w.w);
+  } else {
+    const uint32_t ca = (uint32_t)(3 * h) >> 1;
+    const uint4 wa = philox(make_uint4(ca, (uint32_t)c, s, 2u * u + 1u), k0, k1);
+    const uint4 wb = philox(make_uint4(ca + 1u, (uint32_t)c, s, 2u * u + 1u), k0, k1);
+    if ((h & 1) == 0) {  // pairs 3h, 3h + 1 in call ca, 3h + 2 in ca + 1
+      phi[0] = uniform53(wa.x, wa.y);
+      phi[1] = uniform53(wa.z, wa.w);
+      phi[2] = uniform53(wb.x, wb.y);
+    } else {  // pair 3h in call ca, 3h + 1 and 3h + 2 in ca + 1
+      phi[0] = uniform53(wa.z, wa.w);
+      phi[1] = uniform53(wb.x, wb.y);
+      phi[2] = uniform53(wb.z, wb.w);
+    }
+  }
+}
+
+// Candidate pairs of one (sub)step; thread h takes sorted positions
+// SPT h .. SPT h + SPT - 1, i.e. pairs NP h .. NP h + NP - 1 (NP = SPT / 2),
+// whose uniforms come from one or two Philox calls.  kPassPlain updates
 // global memory; kPassPlainLds computes p the same way and updates the
 // LDS-resident multiplicities (steps fused in one launch); kPassPmax keeps
 // the pre-products in registers and returns this thread's largest p at q;
@@ -544,10 +617,14 @@ template <int CAP, int W, int MODE>
 __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp, double* vg,
                                              int n, int nlive, int tid, int c, uint32_t s,
                                              uint32_t u, double q, bool clamp, int64_t o0,
-                                             int* ncoll, PairRegs<(CAP + 256 * W - 1) / (256 * W)>& R,
+                                             int* ncoll,
+                                             PairRegs<sort_rounds<CAP, W>(),
+                                                      slots_per_thread<CAP, W>()>& R,
                                              int* ndead = nullptr) {
   constexpr int T = 64 * W;
-  constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);
+  constexpr int SPT = slots_per_thread<CAP, W>();
+  constexpr int NP = SPT / 2;  // pairs per thread and round
+  constexpr int I4 = sort_rounds<CAP, W>();
   const int P = nlive >> 1;
   const double S = (double)((nlive & 1) ? nlive : nlive - 1);
   const uint16_t* perm = perm_of(L);
@@ -560,19 +637,29 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
   if (MODE != kPassAdapt) {
     // every pair's slots and sizes first (slots past the pairs clamped into
     // the cell and masked), then the arithmetic
-    double xv[I4][4];
-    double sv[I4][4];
+    double xv[I4][SPT];
+    double sv[I4][SPT];
 #pragma unroll
     for (int i = 0; i < I4; ++i) {
       const int h = T * i + tid;
-      R.o4[i] = make_uint2(0u, 0u);
-      if (2 * h >= P) continue;
-      R.o4[i] = *reinterpret_cast<const uint2*>(&perm[4 * h]);
-      const uint32_t sl[4] = {R.o4[i].x & 0xFFFFu, R.o4[i].x >> 16, R.o4[i].y & 0xFFFFu,
-                              R.o4[i].y >> 16};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t j = min(sl[e], (uint32_t)CAP - 1u);
+      for (int k = 0; k < NP; ++k) R.o[i][k] = 0u;
+      if (NP * h >= P) continue;
+      // positions SPT h ..: 4-byte aligned (8-byte with 4 slots per thread),
+      // inside the permutation array's 2 CAP entries
+      if constexpr (SPT == 4) {
+        const uint2 o2 = *reinterpret_cast<const uint2*>(&perm[4 * h]);
+        R.o[i][0] = o2.x;
+        R.o[i][1] = o2.y;
+      } else {
+        const uint32_t* pw = reinterpret_cast<const uint32_t*>(&perm[SPT * h]);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) R.o[i][k] = pw[k];
+      }
+#pragma unroll
+      for (int e = 0; e < SPT; ++e) {
+        const uint32_t sl = (e & 1) ? (R.o[i][e >> 1] >> 16) : (R.o[i][e >> 1] & 0xFFFFu);
+        const uint32_t j = min(sl, (uint32_t)CAP - 1u);
         xv[i][e] = L.xd[j];
         sv[i][e] = L.rs[j];
       }
@@ -580,14 +667,15 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
 #pragma unroll
     for (int i = 0; i < I4; ++i) {
       const int h = T * i + tid;
-      R.pre[i][0] = R.pre[i][1] = 0.0;
-      if (2 * h >= P) continue;
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
+      for (int e = 0; e < NP; ++e) R.pre[i][e] = 0.0;
+      if (NP * h >= P) continue;
+#pragma unroll
+      for (int e = 0; e < NP; ++e) {
         const double kv = pair_kernel(kind, bgol, sv[i][2 * e], sv[i][2 * e + 1]);
         const double pp = (fmax(xv[i][2 * e], xv[i][2 * e + 1]) * kv) * S;
-        R.pre[i][e] = (2 * h + e < P) ? pp : 0.0;
-        if (MODE == kPassPmax && 2 * h + e < P) pmax = fmax(pmax, pp * q);
+        R.pre[i][e] = (NP * h + e < P) ? pp : 0.0;
+        if (MODE == kPassPmax && NP * h + e < P) pmax = fmax(pmax, pp * q);
       }
     }
     if (MODE == kPassPmax) return pmax;
@@ -600,18 +688,18 @@ __device__ __forceinline__ double team_pairs(CellLds<CAP>& L, const SimDesc* dp,
 #pragma unroll
   for (int i = 0; i < I4; ++i) {
     const int h = T * i + tid;
-    if (2 * h >= P) continue;
-    const uint4 w = philox(make_uint4((uint32_t)h, (uint32_t)c, s, 2u * u + 1u), dp->seed_lo,
-                           dp->seed_hi);
+    if (NP * h >= P) continue;
+    double phis[NP];
+    pair_uniforms<SPT>(h, c, s, u, dp->seed_lo, dp->seed_hi, phis);
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int m = 2 * h + e;
+    for (int e = 0; e < NP; ++e) {
+      const int m = NP * h + e;
       if (m >= P) break;
-      const int a = (int)((e == 0 ? R.o4[i].x : R.o4[i].y) & 0xFFFFu);
-      const int bb = (int)((e == 0 ? R.o4[i].x : R.o4[i].y) >> 16);
+      const int a = (int)(R.o[i][e] & 0xFFFFu);
+      const int bb = (int)(R.o[i][e] >> 16);
       double p = R.pre[i][e] * q;
       if (clamp && p > 1.0) p = 1.0;
-      const double phi = e == 0 ? uniform53(w.x, w.y) : uniform53(w.z, w.w);
+      const double phi = phis[e];
       const long long gamma = collisions(p, phi, dp->status);
       if (sink) {
         sink[sink_base + 2 * m] = (int64_t)((uint64_t)a | ((uint64_t)bb << 32));
@@ -716,7 +804,6 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
                                                   uint32_t* __restrict__ order_flag) {
   constexpr int T = 64 * W;
   constexpr int IT = (CAP + T - 1) / T;
-  constexpr int I4 = (CAP + 4 * T - 1) / (4 * T);
   __shared__ CellLds<CAP> L;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -762,7 +849,7 @@ __global__ void __launch_bounds__(64 * W) k_cells(const SimDesc* __restrict__ de
   }
   const int nlive = team_sum<W>(L, mylive, lane, wv);  // also orders the LDS stores
 
-  PairRegs<I4> R;
+  PairRegs<sort_rounds<CAP, W>(), slots_per_thread<CAP, W>()> R;
   int ncoll = 0;
   unsigned long long live_sum = 0, nsub = 0, steps_done = 0;
   if (!in_lds) {  // one plain step: updates go straight to global memory
