@@ -375,7 +375,8 @@ def main():
     ap.add_argument("--workload", default="grid256",
                     choices=["grid256", "grid64", "golovin", "geometric", "serving", "displace",
                              "kinematic", "condense"])
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (also when the environment sets SDM_TUNE=0)")
     ap.add_argument("--mask", type=lambda x: int(x, 0), default=None,
                     help="fixed class mask (skips the autotuner; e.g. 0x18)")
     ap.add_argument("--waves", type=int, default=None,
@@ -434,6 +435,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuning_note = "default"
+    if os.environ.get("SDM_TUNE", "1").strip() == "0":
+        args.no_tune = True
     if args.mask is not None:
         t = B.sdm_get_tuning(sim.handle)
         t.wave_class_mask = args.mask

@@ -242,8 +242,10 @@ sdm_status sdm_set_tuning(sdm_sim* s, const sdm_tuning* t, void* stream);
  * >= sdm_autotune_scratch_bytes) for trial_steps steps each, apply the
  * fastest to s and, if cache_path is not NULL, record it in that JSON file
  * keyed by device, kernel, n_attr, mode and a cell-size histogram; a cached
- * entry is reused without timing.  s's own state and step counter are not
- * touched.  chosen (optional) receives the tuning.
+ * entry is reused without timing.  cache_path NULL takes the file named by
+ * the environment variable SDM_TUNE_CACHE, when set and not empty (no cache
+ * otherwise).  s's own state and step counter are not touched.  chosen
+ * (optional) receives the tuning.
  */
 size_t sdm_autotune_scratch_bytes(const sdm_sim* s);
 sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_bytes, int32_t trial_steps,

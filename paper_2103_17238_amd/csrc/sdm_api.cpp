@@ -1227,6 +1227,10 @@ extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_byt
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const std::string key = tune_key(s);
   sdm_tuning best{};
+  if (!cache_path) {  // the environment may name a cache for callers that pass none
+    const char* env = std::getenv("SDM_TUNE_CACHE");
+    if (env && *env) cache_path = env;
+  }
   if (cache_path && cache_lookup(cache_path, key, &best)) {
     const sdm_status r = sdm_set_tuning(s, &best, stream);
     if (r == SDM_OK && chosen) *chosen = s->tuning;

@@ -651,10 +651,11 @@ def test_empty_and_tiny(B, orc):
     g.close()
 
 
-def test_autotune_keeps_results_and_caches(B, orc, tmp_path):
+def test_autotune_keeps_results_and_caches(B, orc, tmp_path, monkeypatch):
     """The autotuner times shapes on a scratch copy: the handle's state and
     counter are untouched, results after tuning still match the oracle, and
-    a second handle with the same key reuses the cached choice."""
+    a second handle with the same key reuses the cached choice, named by the
+    call or, with no path passed, by SDM_TUNE_CACHE."""
     st = I.random_cells(64, 900, n_attr=1, rng_seed=91, p_boost=30.0)
     g = GpuRun(B, st)
     scratch = B.workspace_tensor(B.sdm_autotune_scratch_bytes(g.sim.handle))
@@ -680,6 +681,12 @@ def test_autotune_keeps_results_and_caches(B, orc, tmp_path):
     assert t2 == t1
     assert len(open(cache).read().strip().splitlines()) == 1
     g2.close()
+    monkeypatch.setenv("SDM_TUNE_CACHE", cache)
+    g3 = GpuRun(B, st)
+    t3 = B.sdm_autotune(g3.sim.handle, None, trial_steps=2).as_dict()  # no scratch: a cache hit
+    assert t3 == t1
+    assert len(open(cache).read().strip().splitlines()) == 1
+    g3.close()
 
 
 def _sub_state(st, cells):
