@@ -32,7 +32,9 @@
  *     lifetime of the handle; it never allocates or frees device memory.
  *   - The library allocates only the host-side handle and, at the first step
  *     of a simulation or batch, one more HIP stream (default priority) and two
- *     events; sdm_free / sdm_batch_free release them.
+ *     events, plus a second stream and one more event at the first step with
+ *     cells of 2049 to 8192 slots (the 4096- and 8192-slot mid-size classes);
+ *     sdm_free / sdm_batch_free release them.
  *   - Layout is structure-of-arrays: xi[n_slots] (int64), v[n_slots] (float64,
  *     m^3), attrs[n_attr][n_slots] (float64, extra extensive attributes summed
  *     on coalescence like volume), cell_off[n_cells + 1] (int64, slots of cell
@@ -46,8 +48,8 @@
  * word (sdm_status_word).
  *
  * Threading.  Step and moments calls only enqueue work on `stream` and return.
- * Part of a step may run on the library's second stream, which waits for
- * `stream` (an event) and is joined back into it before the call returns, so
+ * Parts of a step may run on the library's own streams, which wait for
+ * `stream` (an event) and are joined back into it before the call returns, so
  * work enqueued on `stream` afterwards sees the step complete.  One handle
  * must not be stepped on two streams at once: a step call (alone or in a
  * batch) on another stream than the one its last steps were enqueued on,

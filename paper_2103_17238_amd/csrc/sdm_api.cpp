@@ -372,7 +372,9 @@ struct Plan {
   ~Plan() {
     if (side.fork) (void)hipEventDestroy(side.fork);
     if (side.join) (void)hipEventDestroy(side.join);
+    if (side.join2) (void)hipEventDestroy(side.join2);
     if (side.stream) (void)hipStreamDestroy(side.stream);
+    if (side.stream2) (void)hipStreamDestroy(side.stream2);
   }
 };
 
@@ -587,6 +589,14 @@ static sdm_status plan_step(Plan* p, int32_t n_steps, hipStream_t st) {
     if (hipStreamCreateWithFlags(&p->side.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->side.fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->side.join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return SDM_EDEVICE;
+    }
+  }
+  // a second side stream once the plan has cells of the 8192- or 4096-slot class
+  if (active > 0 && (p->dev.n_mid[2] > 0 || p->dev.n_mid[1] > 0) && !p->side.stream2) {
+    if (hipStreamCreateWithFlags(&p->side.stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->side.join2, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
       return SDM_EDEVICE;
     }

@@ -170,8 +170,8 @@ struct PlanDev {
 
 // second stream (and fork/join events) for concurrent class launches
 struct SideStream {
-  hipStream_t stream = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t stream = nullptr, stream2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
 };
 
 // launches (sdm_kernels.hip)

@@ -2319,29 +2319,36 @@ static void launch_mid(const PlanDev& p, int cls, uint32_t k_abs, hipStream_t st
 
 hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
                        int waves_per_cell, hipStream_t st, const SideStream& side) {
-  // Two independent groups of launches run on two streams and fill each
-  // other's tails: the cells of up to 256 slots and the mid-size cells on a
-  // second stream, the 384- and 512-slot classes and the big-cell chain on
-  // the caller's stream (joined back through an event).
-  const bool small = p.n_wave[0] > 0 || p.n_wave[1] > 0 || p.n_wave[2] > 0;
-  const bool mid = p.n_mid[0] > 0 || p.n_mid[1] > 0 || p.n_mid[2] > 0 || p.n_mid[3] > 0;
-  const bool large = p.n_wave[3] > 0 || p.n_wave[4] > 0 || p.n_big > 0;
-  const bool fork = side.stream && (small || mid) && large;
-  hipStream_t st2 = st;
-  if (fork) {
+  // Up to three independent groups of launches run on their own streams and
+  // fill each other's tails: A, the cells of up to 256 slots and the
+  // 16384- and 2048-slot mid-size classes, on a side stream; B, the 8192-
+  // and 4096-slot mid-size classes, on a second side stream; L, the 384-
+  // and 512-slot classes and the big-cell chain, on the caller's stream.
+  // A group runs on the caller's stream when nothing runs beside it there;
+  // the side streams wait for the caller's stream (one event) and are
+  // joined back into it (an event each).
+  const bool ga = p.n_wave[0] > 0 || p.n_wave[1] > 0 || p.n_wave[2] > 0 || p.n_mid[3] > 0 ||
+                  p.n_mid[0] > 0;
+  const bool gb = p.n_mid[2] > 0 || p.n_mid[1] > 0;
+  const bool gl = p.n_wave[3] > 0 || p.n_wave[4] > 0 || p.n_big > 0;
+  const bool fa = side.stream && ga && gl;
+  const bool fb = side.stream2 && gb && (ga || gl);
+  const hipStream_t sa = fa ? side.stream : st;
+  const hipStream_t sb = fb ? side.stream2 : st;
+  if (fa || fb) {
     if (hipEventRecord(side.fork, st) != hipSuccess ||
-        hipStreamWaitEvent(side.stream, side.fork, 0) != hipSuccess)
+        (fa && hipStreamWaitEvent(sa, side.fork, 0) != hipSuccess) ||
+        (fb && hipStreamWaitEvent(sb, side.fork, 0) != hipSuccess))
       return hipErrorUnknown;
-    st2 = side.stream;
   }
-  launch_class<256>(p, 2, k_abs, flip, nsteps, waves_per_cell, st2);
-  launch_class<128>(p, 1, k_abs, flip, nsteps, waves_per_cell, st2);
-  launch_class<64>(p, 0, k_abs, flip, nsteps, waves_per_cell, st2);
+  launch_class<256>(p, 2, k_abs, flip, nsteps, waves_per_cell, sa);
+  launch_class<128>(p, 1, k_abs, flip, nsteps, waves_per_cell, sa);
+  launch_class<64>(p, 0, k_abs, flip, nsteps, waves_per_cell, sa);
   for (int t = 0; t < nsteps; ++t) {  // mid-size cells: one launch per step
-    launch_mid<16384>(p, 3, k_abs + t, st2);
-    launch_mid<8192>(p, 2, k_abs + t, st2);
-    launch_mid<4096>(p, 1, k_abs + t, st2);
-    launch_mid<2048>(p, 0, k_abs + t, st2);
+    launch_mid<16384>(p, 3, k_abs + t, sa);
+    launch_mid<8192>(p, 2, k_abs + t, sb);
+    launch_mid<4096>(p, 1, k_abs + t, sb);
+    launch_mid<2048>(p, 0, k_abs + t, sa);
   }
   launch_class<512>(p, 4, k_abs, flip, nsteps, waves_per_cell, st);
   launch_class<384>(p, 3, k_abs, flip, nsteps, waves_per_cell, st);
@@ -2356,8 +2363,11 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nste
                        (unsigned long long*)nullptr, (double*)nullptr,
                        (unsigned long long*)nullptr);
   }
-  if (fork && (hipEventRecord(side.join, st2) != hipSuccess ||
-               hipStreamWaitEvent(st, side.join, 0) != hipSuccess))
+  if (fa && (hipEventRecord(side.join, sa) != hipSuccess ||
+             hipStreamWaitEvent(st, side.join, 0) != hipSuccess))
+    return hipErrorUnknown;
+  if (fb && (hipEventRecord(side.join2, sb) != hipSuccess ||
+             hipStreamWaitEvent(st, side.join2, 0) != hipSuccess))
     return hipErrorUnknown;
   return hipGetLastError();
 }
