@@ -117,8 +117,9 @@ typedef struct {
   int32_t wave_class_mask;   /* bit k (k = 0..4) enables the workgroup-per-cell class of
                                 64, 128, 256, 384, 512 slots; a cell goes to the smallest
                                 enabled class that fits; bit 4 (512) is always on.  Classes
-                                up to 256 slots and the mid-size cells run on a second stream
-                                beside the larger classes and the big-cell kernels */
+                                up to 256 slots and the mid-size cells run on the library's
+                                side streams beside the larger classes and the big-cell
+                                kernels */
   int32_t waves_per_cell;    /* 1, 2, 4 or 8: wavefronts in the workgroup of one cell */
   int32_t big_bucket_target; /* cells on the big-cell path: expected SDs per bucket (a key
                                 range ordered by one workgroup), 32..1024 */
@@ -127,7 +128,12 @@ typedef struct {
                                 the step before, most first) */
   int32_t mid_max_slots;     /* cells of 513..mid_max_slots slots (<= 16384) get one workgroup
                                 each (mid-size kernel); larger ones take the big-cell path
-                                (two launches per step); 0 sends every cell above 512 there */
+                                (two launches per step); 0 sends every cell above 512 there.
+                                -1 (the default) chooses: adaptive cells up to 16384 slots
+                                and plain ones up to 4096 get the mid-size kernel, plain
+                                cells of 4097..16384 slots too when a plan (or batch) has
+                                more than 32 of them, else the big-cell path (faster for a
+                                few cells, slower for many) */
   int32_t big_bucket_cap;    /* big-cell path: longest bucket one workgroup orders in LDS;
                                 longer ones are ranked in global memory (still exact,
                                 slower, SDM_FLAG_BUCKET_OVERFLOW); 0 = 1024, else 1..1024 */

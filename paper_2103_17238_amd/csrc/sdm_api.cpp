@@ -42,13 +42,25 @@ inline int ceil_log2(int64_t x) {
   return b;
 }
 
+// The automatic mid-size limit (mid_max_slots = -1).  A step over a few
+// cells is latency-bound: the big-cell path's two launches take about 15 us
+// for one cell of 4 096 to 16 384 slots, the mid-size kernel 13 us at 4 096,
+// 21 at 8 192 and 36 at 16 384.  Over many cells throughput decides, and
+// there the mid-size kernel is ahead (1 024 cells of 8 192 slots: 184 us per
+// step against 375).  So plain cells above kPlainMidMaxDefault slots take the
+// big-cell path when a plan has at most kAutoBigCells of them.  Adaptive
+// cells keep the mid-size kernel up to its limit (adaptive big cells read
+// one word back per four substep rounds).
+constexpr int32_t kPlainMidMaxDefault = 4096;
+constexpr int64_t kAutoBigCells = 32;
+
 sdm_tuning default_tuning() {
   sdm_tuning t;
   t.wave_class_mask = sdm::kClassAll;
   t.waves_per_cell = 1;
   t.big_bucket_target = 256;
   t.lpt_order = 1;
-  t.mid_max_slots = sdm::kMidCapMax;
+  t.mid_max_slots = -1;  // automatic
   t.big_bucket_cap = 0;
   return t;
 }
@@ -57,7 +69,7 @@ bool tuning_ok(const sdm_tuning& t) {
   const int w = t.waves_per_cell;
   return (w == 1 || w == 2 || w == 4 || w == 8) && t.big_bucket_target >= sdm::kMinBucketTarget &&
          t.big_bucket_target <= 1024 && (t.wave_class_mask & ~sdm::kClassAll) == 0 &&
-         t.mid_max_slots >= 0 && t.mid_max_slots <= sdm::kMidCapMax && t.big_bucket_cap >= 0 &&
+         t.mid_max_slots >= -1 && t.mid_max_slots <= sdm::kMidCapMax && t.big_bucket_cap >= 0 &&
          t.big_bucket_cap <= 1024;
 }
 
@@ -212,7 +224,22 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
   std::vector<Item> items[sdm::kNumClasses];
   std::vector<Item> mids[sdm::kNumMid];
   const int mask = tu.wave_class_mask | sdm::kClassTop;
+  // the mid-size limit of plain and of adaptive cells (automatic: see
+  // kAutoBigCells)
+  int64_t mid_plain = tu.mid_max_slots, mid_adapt = tu.mid_max_slots;
+  if (tu.mid_max_slots < 0) {
+    int64_t upper = 0;  // plain cells the automatic rule may move
+    for (auto* s : ms)
+      if (!s->cfg.adaptive)
+        for (int c = 0; c < s->cfg.n_cells; ++c) {
+          const int64_t n = s->off[c + 1] - s->off[c];
+          upper += (n > kPlainMidMaxDefault && n <= sdm::kMidCapMax) ? 1 : 0;
+        }
+    mid_plain = upper <= kAutoBigCells ? kPlainMidMaxDefault : sdm::kMidCapMax;
+    mid_adapt = sdm::kMidCapMax;
+  }
   for (int i = 0; i < (int)ms.size(); ++i) {
+    const int64_t mid_max = ms[i]->cfg.adaptive ? mid_adapt : mid_plain;
     const auto& off = ms[i]->off;
     const int C = ms[i]->cfg.n_cells;
     for (int c = 0; c < C; ++c) {
@@ -224,7 +251,7 @@ static void build_tables(const std::vector<sdm_sim*>& ms, const sdm_tuning& tu, 
         items[k].push_back({n, i, c, ms[i]->cfg.adaptive});
         continue;
       }
-      if (n <= tu.mid_max_slots) {
+      if (n <= mid_max) {
         int k = 0;
         while (n > sdm::mid_cap(k)) ++k;
         mids[k].push_back({n, i, c, ms[i]->cfg.adaptive});
@@ -1289,12 +1316,13 @@ extern "C" sdm_status sdm_autotune(sdm_sim* s, void* scratch, size_t scratch_byt
       if (((m >> k) & 1) && has_small[k]) useful = true;
     if (useful) masks.push_back(m);
   }
-  std::vector<int> mids = has_mid && !s->cfg.adaptive ? std::vector<int>{sdm::kMidCapMax, 0}
-                                                      : std::vector<int>{sdm::kMidCapMax};
+  std::vector<int> mids = has_mid && !s->cfg.adaptive
+                              ? std::vector<int>{sdm::kMidCapMax, kPlainMidMaxDefault, 0}
+                              : std::vector<int>{-1};
   std::vector<sdm_tuning> cands;
   for (int mm : mids) {
     // the bucket size matters only when some cell takes the big-cell path
-    const bool bigs = has_big || (mm == 0 && has_mid);
+    const bool bigs = has_big || (has_mid && mm >= 0 && mm < sdm::kMidCapMax);
     const std::vector<int> targets =
         bigs ? std::vector<int>{64, 128, 256, 512} : std::vector<int>{256};
     bool any_small = false;

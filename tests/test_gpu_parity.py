@@ -315,6 +315,21 @@ def test_adaptive_attributes_many_collisions(B, orc, boost, uniform):
     assert _compare_run(B, orc, st, 4, label=f"adaptive-attrs-{boost}-{uniform}")
 
 
+@pytest.mark.parametrize("mid_max", [16384, -1])
+def test_plain_mid_and_big_routes(B, orc, mid_max):
+    """Plain Golovin cells of up to 16384 slots: every mid-size class
+    (mid_max_slots = 16384), or the automatic route (the default: with at
+    most 32 such cells, those above 4096 slots on the big-cell path);
+    bit-exact against the oracle, pair logs equal."""
+    st = I.random_cells(24, 16384, n_attr=1, rng_seed=41, p_boost=1e3)
+    tu = dict(mid_max_slots=mid_max)
+    g = B.Sim(st)
+    assert B.sdm_get_tuning(g.handle).mid_max_slots == -1
+    g.close()
+    say(f"plain mid-size and big routes, mid_max_slots={mid_max}")
+    assert _compare_run(B, orc, st, 6, sink=True, tuning=tu, label=f"mid{mid_max}")
+
+
 def test_adaptive_mid_cells_bit_exact(B, orc):
     """Adaptive substeps in the mid-size kernel (cells of 513..16384 slots)."""
     st = I.random_cells(12, 3000, n_attr=2, rng_seed=33, p_boost=1e3)
