@@ -33,7 +33,7 @@
  *   - The library allocates only the host-side handle and, at the first step
  *     of a simulation or batch, one more HIP stream (default priority) and two
  *     events, plus a second stream and one more event at the first step with
- *     cells of 2049 to 8192 slots (the 4096- and 8192-slot mid-size classes);
+ *     cells in the 4096- or 8192-slot mid-size classes (see mid_max_slots);
  *     sdm_free / sdm_batch_free release them.
  *   - Layout is structure-of-arrays: xi[n_slots] (int64), v[n_slots] (float64,
  *     m^3), attrs[n_attr][n_slots] (float64, extra extensive attributes summed

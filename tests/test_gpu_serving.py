@@ -62,9 +62,9 @@ def test_served_alone_equals_in_mix(B, tight, k):
 
 def test_served_mix_equals_oracle(B, orc):
     """A mix spanning the serving range of SD counts (2^10..2^16), with
-    requests in every mid-size class (1024..16384 slots) and on the big-cell
-    path (above 16384 slots), both kernels, under a budget that forces
-    queueing.  Every served result equals the request's oracle run: the
+    requests of every size range (1024..16384 slots: the mid-size kernel up
+    to 4096, the big-cell path above under the default automatic route) and
+    above 16384 slots, both kernels, under a budget that forces queueing.  Every served result equals the request's oracle run: the
     multiplicities bit for bit, volumes within 1e-12 relative (Golovin
     requests bit-exact), and the mass spectrum within 1 %."""
     from paper_2103_17238_amd.serving import GpuExecutor, Server
