@@ -122,7 +122,9 @@ typedef struct {
                                 kernels */
   int32_t waves_per_cell;    /* 1, 2, 4 or 8: wavefronts in the workgroup of one cell */
   int32_t big_bucket_target; /* cells on the big-cell path: expected SDs per bucket (a key
-                                range ordered by one workgroup), 32..1024 */
+                                range ordered by one workgroup), 32..1024; 0 (the default)
+                                chooses per cell: 128 up to 32768 slots, 256 up to 65536,
+                                512 above */
   int32_t lpt_order;         /* 1: dispatch cells by descending size (adaptive cells: at the
                                 first step; after it they go by the substeps they took in
                                 the step before, most first) */
