@@ -39,6 +39,9 @@ sys.path.insert(0, ROOT)
 METRIC = "super-droplet-steps/s (coalescence) + % HBM roofline; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
+# steps per serving tick: paired runs on 2048 requests of the serving trace
+# gave p50 13.6-15.8 ms, p99 27-31 ms at 50 against 14.1-18.2 and 32-42 ms at 25
+SERVE_TICK = 50
 
 
 def note(msg):
@@ -337,10 +340,10 @@ def serving_c5(n_requests, rate, baseline_prefix, small_budget_prefix, steps=600
     budget = int(0.8 * free)
     # warm-up: kernels loaded, allocator primed (its own short trace)
     warm = I.serving_requests(16, rate_per_s=4000.0, n_steps=20, rng_seed=99)
-    Server(GpuExecutor(), budget_bytes=budget, steps_per_tick=25).run(warm, I.request_state)
+    Server(GpuExecutor(), budget_bytes=budget, steps_per_tick=SERVE_TICK).run(warm, I.request_state)
     note(f"serving: {n_requests} requests at {rate:g}/s")
     ex = GpuExecutor()
-    stats = Server(ex, budget_bytes=budget, steps_per_tick=25).run(reqs, I.request_state)
+    stats = Server(ex, budget_bytes=budget, steps_per_tick=SERVE_TICK).run(reqs, I.request_state)
     ex.close()
     served = stats.summary()
     served.update(requests=n_requests, budget_bytes=budget,
@@ -351,7 +354,7 @@ def serving_c5(n_requests, rate, baseline_prefix, small_budget_prefix, steps=600
     base.update(requests=baseline_prefix, note=f"first {baseline_prefix} requests of the trace")
     note(f"serving: 64 MiB budget on the first {small_budget_prefix}")
     ex = GpuExecutor()
-    small = Server(ex, budget_bytes=64 * 2 ** 20, steps_per_tick=25).run(
+    small = Server(ex, budget_bytes=64 * 2 ** 20, steps_per_tick=SERVE_TICK).run(
         reqs[:small_budget_prefix], I.request_state)
     ex.close()
     tight = small.summary()
@@ -839,9 +842,9 @@ def serve_bench(args):
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
     ex = GpuExecutor()
-    srv = Server(ex, budget_bytes=budget, steps_per_tick=25)
+    srv = Server(ex, budget_bytes=budget, steps_per_tick=SERVE_TICK)
     # warm-up: kernels compiled / loaded, allocator primed
-    Server(GpuExecutor(), budget_bytes=budget, steps_per_tick=25).run(reqs[:8], I.request_state)
+    Server(GpuExecutor(), budget_bytes=budget, steps_per_tick=SERVE_TICK).run(reqs[:8], I.request_state)
     stats = srv.run(reqs, I.request_state)
     ex.close()
     served = stats.summary()
@@ -867,7 +870,7 @@ def serve_bench(args):
                         "nsd_2^10..2^16_600_steps",
             "parallelism": "1 GPU, continuous batching, one shared launch per step",
             "budget_bytes": budget,
-            "steps_per_tick": 25,
+            "steps_per_tick": SERVE_TICK,
         },
         "serving": served,
         "one_at_a_time": dict(base, requests=len(base_reqs)),

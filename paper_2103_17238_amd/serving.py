@@ -94,7 +94,7 @@ class Server:
     steps_per_tick: steps per shared launch sequence between admissions.
     """
 
-    def __init__(self, executor, budget_bytes, max_resident=4096, steps_per_tick=25,
+    def __init__(self, executor, budget_bytes, max_resident=4096, steps_per_tick=50,
                  clock=time.perf_counter, sleep=time.sleep):
         self.ex = executor
         self.budget = int(budget_bytes)
