@@ -554,7 +554,7 @@ def main():
             "n_attr": A,
             "kernel": "geometric" if state.kernel == 1 else "golovin",
             "adaptive": bool(state.adaptive),
-            "parallelism": ("1 GPU, concurrent cell launches per step (two streams)" if two
+            "parallelism": ("1 GPU, concurrent cell launches per step (two of the library's streams)" if two
                             else "1 GPU, one fused launch per step") if cell_grid else "1 GPU",
             "tuning": tuning,
             "tuning_source": tuning_note,

@@ -168,7 +168,7 @@ struct PlanDev {
   uint32_t* aactive;  // device word: cells still stepping
 };
 
-// second stream (and fork/join events) for concurrent class launches
+// the plan's side streams (and fork/join events) for concurrent class launches
 struct SideStream {
   hipStream_t stream = nullptr, stream2 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
