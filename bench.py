@@ -586,7 +586,9 @@ def main():
     note(f"{total_ms / K:.4f} ms per step; batching and fusion figures")
     if cell_grid and not args.no_batching_check:
         line["batching"] = batched_vs_separate(host_state, tuning)
-        line["fusion"] = fused_vs_single(host_state, tuning)
+        # the whole timed job (the same number of steps from the initial
+        # state) in one call, beside one call per step
+        line["fusion"] = fused_vs_single(host_state, tuning, steps=args.steps)
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(host_state, args.cpu_cells, args.cpu_steps)
