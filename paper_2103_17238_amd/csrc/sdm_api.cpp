@@ -502,6 +502,9 @@ static sdm_status plan_setup(Plan* p, hipStream_t st, bool sync_end = true) {
   d.n_big = (int)p->T.big.size();
   d.chunks = reinterpret_cast<const BigChunk*>(w + L.chunks);
   d.n_chunks = (int)p->T.chunks.size();
+  int nb_max = 1;
+  for (const auto& t : p->T.big) nb_max = std::max(nb_max, (int)t.nb);
+  d.big_hist_bytes = (unsigned)(sizeof(uint32_t) * (size_t)(nb_max + 1));
   d.buckets = reinterpret_cast<const BigBucket*>(w + L.buckets);
   d.n_buckets = (int)p->T.buckets.size();
   d.ekey = reinterpret_cast<unsigned long long*>(w + L.ekey);

@@ -15,8 +15,8 @@ constexpr int kNumMid = 4;        // mid-size capacities 2048, 4096, 8192, 16384
 constexpr int kMidCapMax = 16384;
 constexpr int kBigChunkUnit = 1024;   // slots per Philox round of a big-cell key block
 constexpr int kBigMaxChunks = 256;    // key blocks per big cell, at most
-constexpr int kBigMaxBuckets = 8192;  // buckets per big cell, at most (one LDS histogram)
-constexpr int64_t kBigMaxSlots = 8388608;  // slots per cell, at most (kBigMaxBuckets x 1024)
+constexpr int kBigMaxBuckets = 16384;  // buckets per big cell, at most (one LDS histogram)
+constexpr int64_t kBigMaxSlots = 8388608;  // slots per cell, at most (kBigMaxBuckets x 512)
 constexpr int kAbigPairs = 256;   // pairs per block of the adaptive big-cell pair pass
 constexpr int kAbigRoundsPerCheck = 4;  // adaptive big-cell substep rounds between host checks
 constexpr int kMinBucketTarget = 32;
@@ -139,6 +139,7 @@ struct PlanDev {
   int n_big;
   const BigChunk* chunks;
   int n_chunks;
+  unsigned big_hist_bytes;  // LDS of a key block: the largest bucket count + 1 words
   const BigBucket* buckets;
   int n_buckets;
   // entries of every big cell, by chunk, grouped by bucket: (key << 32 |

@@ -1251,7 +1251,9 @@ __global__ void __launch_bounds__(kBigKeyThreads) k_big_keys(
     const BigChunk* __restrict__ chunks, uint32_t* __restrict__ offs,
     unsigned long long* __restrict__ ekey, long long* __restrict__ exi,
     double* __restrict__ ev, uint32_t k_abs, const BigAdapt* __restrict__ astate) {
-  __shared__ uint32_t hist[kBigMaxBuckets + 1];
+  // the bucket histogram: nb + 1 words, nb the largest bucket count of the
+  // launch's cells (dynamic LDS, up to kBigMaxBuckets + 1 words)
+  extern __shared__ uint32_t hist[];
   __shared__ int red[kBigKeyThreads / 64];
   const BigChunk ch = chunks[blockIdx.x];
   const BigTask tk = big[ch.task];
@@ -2243,6 +2245,8 @@ void set_lds_limits() {
   if (done) return;
   done = true;
   const int lim = 160 * 1024;
+  (void)hipFuncSetAttribute((const void*)k_big_keys, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(uint32_t) * (kBigMaxBuckets + 1));
   (void)hipFuncSetAttribute((const void*)k_cells_mid<2048, mid_waves(2048), false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void*)k_cells_mid<2048, mid_waves(2048), true>,
@@ -2353,8 +2357,8 @@ hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nste
   launch_class<512>(p, 4, k_abs, flip, nsteps, waves_per_cell, st);
   launch_class<384>(p, 3, k_abs, flip, nsteps, waves_per_cell, st);
   for (int t = 0; t < nsteps && p.n_chunks > 0; ++t) {  // big cells: two launches per step
-    hipLaunchKernelGGL(k_big_keys, dim3(p.n_chunks), dim3(kBigKeyThreads), 0, st, p.desc, p.big,
-                       p.chunks, p.offs, p.ekey, p.exi, p.ev, k_abs + t,
+    hipLaunchKernelGGL(k_big_keys, dim3(p.n_chunks), dim3(kBigKeyThreads), p.big_hist_bytes, st,
+                       p.desc, p.big, p.chunks, p.offs, p.ekey, p.exi, p.ev, k_abs + t,
                        (const BigAdapt*)nullptr);
     hipLaunchKernelGGL(k_big_bucket<false>, dim3(p.n_buckets), dim3(kBigThreads), 0, st, p.desc,
                        p.big, p.buckets, (const uint32_t*)p.offs,
@@ -2380,8 +2384,8 @@ hipError_t launch_abig_init(const PlanDev& p, uint32_t k_abs, hipStream_t st) {
 
 hipError_t launch_abig_round(const PlanDev& p, uint32_t k_abs, uint32_t round, hipStream_t st) {
   const uint32_t q = round & 1u;
-  hipLaunchKernelGGL(k_big_keys, dim3(p.n_achunks), dim3(kBigKeyThreads), 0, st, p.desc, p.big,
-                     p.achunks, p.offs, p.ekey, p.exi, p.ev, k_abs,
+  hipLaunchKernelGGL(k_big_keys, dim3(p.n_achunks), dim3(kBigKeyThreads), p.big_hist_bytes, st,
+                     p.desc, p.big, p.achunks, p.offs, p.ekey, p.exi, p.ev, k_abs,
                      (const BigAdapt*)p.astate[q]);
   hipLaunchKernelGGL(k_big_bucket<true>, dim3(p.n_abuckets), dim3(kBigThreads), 0, st, p.desc,
                      p.big, p.abuckets, (const uint32_t*)p.offs,

@@ -184,6 +184,20 @@ def test_big_cell_several_key_groups(B, orc):
     assert _compare_run(B, orc, st, 3, label="golovin-2^19")
 
 
+def test_big_cell_maximum_size(B, orc):
+    """A cell of the largest size a layout may have (8 388 608 SDs): 256 key
+    blocks of 32 768 slots, 16 384 buckets of about 512 entries (none past
+    the LDS stage); two steps bit-exact with the pair log, status clean."""
+    n = 8388608
+    st = I.golovin_box(n, seed=7)
+    say("golovin box 2^23 (largest cell)")
+    assert _compare_run(B, orc, st, 2, label="golovin-2^23")
+    g = B.Sim(st)
+    g.step(1)
+    assert B.sdm_status_word(g.handle) == 0
+    g.close()
+
+
 def test_big_golovin_box(B, orc):
     """One 2^17-SD cell (the big-cell path) for 20 steps, bit-exact."""
     st = I.golovin_box(2 ** 17)
