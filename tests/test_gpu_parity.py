@@ -718,6 +718,46 @@ def test_autotune_keeps_results_and_caches(B, orc, tmp_path, monkeypatch):
     g3.close()
 
 
+def test_large_batch_many_members(B, orc):
+    """512 simulations in one batch (one cell each, 2..600 SDs: every
+    workgroup-per-cell class and the smallest mid-size class), plain and
+    adaptive, each with its own seed, a third of them with a step limit
+    inside the run: every member equals its own oracle run bit for bit and
+    its step counter stops at its limit."""
+    import torch
+
+    rng = np.random.default_rng(5)
+    states, limits = [], []
+    for i in range(512):
+        st = I.golovin_box(int(rng.integers(2, 601)), seed=1000 + i)
+        st.adaptive = bool(i % 2)
+        states.append(st)
+        limits.append(int(rng.integers(1, 6)) if i % 3 == 0 else None)
+    say("batch of 512 simulations")
+    runs = [GpuRun(B, st) for st in states]
+    for r, lim in zip(runs, limits):
+        if lim is not None:
+            B.sdm_set_step_limit(r.sim.handle, lim)
+    handles = [r.sim.handle for r in runs]
+    ws = B.workspace_tensor(B.sdm_batch_workspace_bytes(handles))
+    b = B.sdm_batch_create(handles, ws)
+    B.sdm_batch_step(b, 2)
+    B.sdm_batch_step(b, 4)
+    torch.cuda.synchronize()
+    for r, st, lim in zip(runs, states, limits):
+        steps = 6 if lim is None else min(6, lim)
+        o = st.copy()
+        cfg = ocfg(orc, o)
+        for s in range(steps):
+            orc.step(cfg, o.xi, o.v, o.attrs, o.cell_off, s)
+        xi, v, _ = r.state()
+        assert B.sdm_get_step(r.sim.handle) == steps
+        assert np.array_equal(xi, o.xi) and np.array_equal(v, o.v), (st.n_slots, st.adaptive)
+    B.sdm_batch_free(b)
+    for r in runs:
+        r.close()
+
+
 def _sub_state(st, cells):
     """Only the given cells keep their slots (cell indices unchanged)."""
     counts = np.diff(st.cell_off)
