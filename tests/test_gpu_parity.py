@@ -187,7 +187,9 @@ def test_big_cell_several_key_groups(B, orc):
 def test_big_cell_maximum_size(B, orc):
     """A cell of the largest size a layout may have (8 388 608 SDs): 256 key
     blocks of 32 768 slots, 16 384 buckets of about 512 entries (none past
-    the LDS stage); two steps bit-exact with the pair log, status clean."""
+    the LDS stage); two steps bit-exact with the pair log, status clean, and
+    the cell's moments (one workgroup over all its slots) against the
+    oracle's: the int64 count exact, the sums within 2 ceil(log2 n) ulps."""
     n = 8388608
     st = I.golovin_box(n, seed=7)
     say("golovin box 2^23 (largest cell)")
@@ -195,7 +197,14 @@ def test_big_cell_maximum_size(B, orc):
     g = B.Sim(st)
     g.step(1)
     assert B.sdm_status_word(g.handle) == 0
+    gm = g.moments()
+    xi, v, at = g.state()
     g.close()
+    om = orc.moments(ocfg(orc, st), xi, v, at, st.cell_off)
+    assert np.array_equal(gm["m0"], om["m0"])
+    bound = 2 * np.ceil(np.log2(n)) * 2.0 ** -53
+    for k in ("m1", "m2"):
+        assert rel_close(gm[k], om[k], bound), k
 
 
 def test_big_golovin_box(B, orc):
