@@ -894,7 +894,7 @@ sdm_status sdm_condensation_step(sdm_sim* s, const sdm_cond_config* cc, const do
   const int64_t ns = s->cfg.n_slots;
   if (sdm::launch_condense(s->xi, s->v, s->attrs + (int64_t)cc->dry_volume_attr * ns,
                            s->attrs + (int64_t)cc->kappa_attr * ns, s->cell_off, s->cfg.n_cells,
-                           max_cell, temperature, pressure, saturation, cc->dt_s,
+                           ns, temperature, pressure, saturation, cc->dt_s,
                            cc->max_iter > 0 ? cc->max_iter : 32, st) != hipSuccess)
     return SDM_EDEVICE;
   // the simulation is busy on `st` until this event (its plan's token)

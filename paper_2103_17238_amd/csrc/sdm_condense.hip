@@ -20,14 +20,15 @@
 // the bracket closes in on the iterate by the sign of g; the iteration stops
 // when a step is at most 1e-14 of x, or after max_iter iterations.
 //
-// Data: each thread takes slot j = part 256 + tid of one cell (blockIdx.x
-// the cell, blockIdx.y the 256-slot part), so the reads of xi, v and the two
-// attributes are coalesced; the cell's ambient terms are computed once per
-// block.  One slot per thread keeps the registers low and the occupancy high:
-// the Newton iteration is a chain of dependent fp64 operations, and it is the
-// other wavefronts of the SIMD that hide its latency.  Bound: HBM for the state (40 B per live slot:
-// xi, v, dry volume and kappa dry volume read, v written), fp64 ALU for the
-// exp / sqrt / cbrt of the Newton iterations.
+// Data: each thread takes one slot, blocks of 256 consecutive slots across
+// cell boundaries (every wavefront but the last full), so the reads of xi,
+// v and the two attributes are coalesced; each cell's ambient terms are
+// computed once per block that holds its slots.  One slot per thread keeps
+// the registers low and the occupancy high: the Newton iteration is a chain
+// of dependent fp64 operations, and it is the other wavefronts of the SIMD
+// that hide its latency.  Bound: HBM for the state (40 B per live slot: xi,
+// v, dry volume and kappa dry volume read, v written), fp64 ALU for the exp
+// / sqrt / cbrt of the Newton iterations.
 #include "sdm_internal.hpp"
 
 namespace sdm {
@@ -62,41 +63,84 @@ __device__ __forceinline__ void s_eq_and_slope(double x, double rd3, double kapp
   ds = f2 * ((rd3 * kappa) * (1.5 * r) / (den * den) - f1 * a / (2.0 * r3));
 }
 
+// ambient terms of a cell: c = 2 dt / (F_k + F_d), A, S
+__device__ __forceinline__ void cell_terms(double T, double p, double S, double dt, double& c,
+                                           double& a, double& s) {
+  const double es = 611.2 * exp(17.67 * (T - 273.15) / (T - 29.65));
+  const double D = kD0 * pow(T / 273.15, 1.94) * (101325.0 / p);
+  const double fk = (kLv / (kRv * T) - 1.0) * kLv * kRhoW / (kKair * T);
+  const double fd = kRhoW * kRv * T / (D * es);
+  c = 2.0 * dt / (fk + fd);
+  a = 2.0 * kSigma / (kRhoW * kRv * T);
+  s = S;
+}
+
+// last cell c with cell_off[c] <= j (cell_off[n_cells] = n_slots > j)
+__device__ __forceinline__ int cell_of(const int64_t* __restrict__ off, int n_cells, int64_t j) {
+  int lo = 0, hi = n_cells;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One block per kCondPart consecutive slots, across cell boundaries, so that
+// every wavefront but the last is full.  The block finds the cell of its
+// first slot (one binary search), reads the offsets of the next kCondPart
+// cells into LDS, and lane t computes the ambient terms of cell c0 + t when
+// that cell has slots in the block; a thread finds its cell by a binary
+// search in that window (a global one, and its own terms, only when more
+// than kCondPart cells, most of them empty, lie inside the block).
 __global__ void __launch_bounds__(kCondThreads) k_condense(
     const int64_t* __restrict__ xi, double* __restrict__ v, const double* __restrict__ vdry,
-    const double* __restrict__ kvdry, const int64_t* __restrict__ cell_off,
-    const double* __restrict__ temp, const double* __restrict__ pres,
+    const double* __restrict__ kvdry, const int64_t* __restrict__ cell_off, int n_cells,
+    int64_t n_slots, const double* __restrict__ temp, const double* __restrict__ pres,
     const double* __restrict__ sat, double dt, int max_iter) {
-  const int c = blockIdx.x;
-  const int64_t o0 = cell_off[c];
-  const int64_t n = cell_off[c + 1] - o0;
-  const int64_t base = (int64_t)blockIdx.y * kCondPart;
-  if (base >= n) return;
-  const int64_t j = base + threadIdx.x;
+  __shared__ int64_t woff[kCondPart + 1];
+  __shared__ double wc[kCondPart], wa[kCondPart], ws[kCondPart];
+  __shared__ int c0s;
+  const int tid = threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * kCondPart;
+  const int64_t j = s0 + tid;
   long long x_ = 0;
   double v_ = 0.0, vd = 0.0, kv = 0.0;
-  if (j < n) x_ = xi[o0 + j];
+  if (j < n_slots) x_ = xi[j];
   if (x_ > 0) {  // the state first (coalesced), then the solve
-    v_ = v[o0 + j];
-    vd = vdry[o0 + j];
-    kv = kvdry[o0 + j];
+    v_ = v[j];
+    vd = vdry[j];
+    kv = kvdry[j];
   }
-  // the cell's ambient terms, by one thread for the block (a pow and an exp
-  // would otherwise cost each wavefront as much as its droplets)
-  __shared__ double amb[3];
-  if (threadIdx.x == 0) {
-    const double T = temp[c], p = pres[c];
-    const double es = 611.2 * exp(17.67 * (T - 273.15) / (T - 29.65));
-    const double D = kD0 * pow(T / 273.15, 1.94) * (101325.0 / p);
-    const double fk = (kLv / (kRv * T) - 1.0) * kLv * kRhoW / (kKair * T);
-    const double fd = kRhoW * kRv * T / (D * es);
-    amb[0] = 2.0 * dt / (fk + fd);
-    amb[1] = 2.0 * kSigma / (kRhoW * kRv * T);
-    amb[2] = sat[c];
+  if (tid == 0) c0s = cell_of(cell_off, n_cells, s0);
+  __syncthreads();
+  const int c0 = c0s;
+  woff[tid] = cell_off[min(c0 + tid, n_cells)];
+  if (tid == 0) woff[kCondPart] = cell_off[min(c0 + kCondPart, n_cells)];
+  __syncthreads();
+  {  // lane t: the terms of cell c0 + t if it has slots in this block
+    const int c = c0 + tid;
+    if (c < n_cells && woff[tid] < s0 + kCondPart && woff[tid + 1] > s0 &&
+        woff[tid + 1] > woff[tid])
+      cell_terms(temp[c], pres[c], sat[c], dt, wc[tid], wa[tid], ws[tid]);
   }
   __syncthreads();
   if (x_ <= 0) return;
-  const double cc = amb[0], a = amb[1], S = amb[2];
+  double cc, a, S;
+  if (j < woff[kCondPart]) {  // the cell inside the window
+    int lo = 0, hi = kCondPart;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (woff[mid] <= j) lo = mid;
+      else hi = mid;
+    }
+    cc = wc[lo];
+    a = wa[lo];
+    S = ws[lo];
+  } else {
+    const int c = cell_of(cell_off, n_cells, j);
+    cell_terms(temp[c], pres[c], sat[c], dt, cc, a, S);
+  }
   const double kappa = vd > 0.0 ? kv / vd : 0.0;
   const double rd3 = vd / kFourPi3;
   const double rd = cbrt(rd3);
@@ -120,17 +164,17 @@ __global__ void __launch_bounds__(kCondThreads) k_condense(
     if (done) break;
   }
   const double r1 = sqrt(x);
-  v[o0 + j] = kFourPi3 * (x * r1);
+  v[j] = kFourPi3 * (x * r1);
 }
 
 hipError_t launch_condense(const int64_t* xi, double* v, const double* vdry, const double* kvdry,
-                           const int64_t* cell_off, int n_cells, int64_t max_cell,
+                           const int64_t* cell_off, int n_cells, int64_t n_slots,
                            const double* temp, const double* pres, const double* sat, double dt,
                            int max_iter, hipStream_t st) {
-  if (n_cells <= 0 || max_cell <= 0) return hipSuccess;
-  const unsigned parts = (unsigned)((max_cell + kCondPart - 1) / kCondPart);
-  hipLaunchKernelGGL(k_condense, dim3((unsigned)n_cells, parts), dim3(kCondThreads), 0, st, xi,
-                     v, vdry, kvdry, cell_off, temp, pres, sat, dt, max_iter);
+  if (n_cells <= 0 || n_slots <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n_slots + kCondPart - 1) / kCondPart);
+  hipLaunchKernelGGL(k_condense, dim3(blocks), dim3(kCondThreads), 0, st, xi, v, vdry, kvdry,
+                     cell_off, n_cells, n_slots, temp, pres, sat, dt, max_iter);
   return hipGetLastError();
 }
 

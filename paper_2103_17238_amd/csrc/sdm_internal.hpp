@@ -184,9 +184,9 @@ struct SideStream {
 hipError_t launch_step(const PlanDev& p, uint32_t k_abs, uint32_t flip, int nsteps,
                        int waves_per_cell, hipStream_t st, const SideStream& side);
 // Diffusional growth of every live super-droplet of one simulation
-// (sdm_condense.hip): one block per (cell, 256-slot part).
+// (sdm_condense.hip): one block per 256 consecutive slots.
 hipError_t launch_condense(const int64_t* xi, double* v, const double* vdry, const double* kvdry,
-                           const int64_t* cell_off, int n_cells, int64_t max_cell,
+                           const int64_t* cell_off, int n_cells, int64_t n_slots,
                            const double* temp, const double* pres, const double* sat, double dt,
                            int max_iter, hipStream_t st);
 // Adaptive big cells: the start of an outer step (every cell's state
