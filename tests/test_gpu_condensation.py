@@ -148,6 +148,31 @@ def test_condensation_grid_sampled(B):
     _compare(v_g[sl], v, "grid256 sample", st.xi[sl], st.attrs[:, sl], sub_off, sub_amb, 1.0)
 
 
+def test_condensation_runs_of_empty_cells(B):
+    """Cells of up to 60 SDs separated by runs of 300 empty cells: a block
+    of 256 consecutive slots spans more cells than its window of offsets, so
+    some threads take the global search for their cell (and compute their
+    cell's terms themselves); every live wet volume against the oracle."""
+    base = I.aerosol_cells(12, 60, n_attr=2, rng_seed=5)
+    counts = []
+    for c in np.diff(base.cell_off):
+        counts += [0] * 300 + [int(c)]
+    cell_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    st = I.State(base.xi.copy(), base.v.copy(), base.attrs.copy(), cell_off)
+    assert st.n_cells == 12 * 301 and st.n_slots == base.n_slots
+    amb = I.ambient(st.n_cells, seed=13, s_lo=0.99, s_hi=1.01)
+    sim = B.Sim(st)
+    T, p, S = _dev(amb["T"]), _dev(amb["p"]), _dev(amb["S"])
+    B.sdm_condensation_step(sim.handle, _cond(B, 1.0), T, p, S)
+    _, v_g, _ = sim.state()
+    sim.close()
+    v = st.v.copy()
+    cd.step(st.xi, v, st.attrs, st.cell_off, amb["T"], amb["p"], amb["S"], 1.0, 0, 1)
+    _compare(v_g, v, "runs of empty cells", st.xi, st.attrs, st.cell_off, amb, 1.0)
+    dead = st.xi == 0
+    assert np.array_equal(v_g[dead], st.v[dead])
+
+
 def test_condensation_invalid_arguments(B):
     import torch
 
