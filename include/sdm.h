@@ -132,10 +132,12 @@ typedef struct {
                                 each (mid-size kernel); larger ones take the big-cell path
                                 (two launches per step); 0 sends every cell above 512 there.
                                 -1 (the default) chooses: adaptive cells up to 16384 slots
-                                and plain ones up to 4096 get the mid-size kernel, plain
-                                cells of 4097..16384 slots too when a plan (or batch) has
-                                more than 32 of them, else the big-cell path (faster for a
-                                few cells, slower for many) */
+                                get the mid-size kernel; plain cells of 4097..16384 slots
+                                too when a plan (or batch) has more than 32 of them, else
+                                the big-cell path (faster for a few cells, slower for many);
+                                plain cells of 513..4096 slots the mid-size kernel, or the
+                                big-cell path when the plan uses it anyway and has at most
+                                32 of them */
   int32_t big_bucket_cap;    /* big-cell path: longest bucket one workgroup orders in LDS;
                                 longer ones are ranked in global memory (still exact,
                                 slower, SDM_FLAG_BUCKET_OVERFLOW); 0 = 1024, else 1..1024 */
